@@ -1,0 +1,61 @@
+"""Plant plausible mistakes in a copy of the oracle (on the CPU) and check
+that the pins catch each one.  Several mutations are the literal forms of
+passages that are garbled in the paper (the 3/2 prefactor of f_sigma, the
+coefficient 4 of the IR force term, the yield test T >= sigma_y, the
+deviator sigma - Tr(sigma) I, the interpolation denominator of Eq. 37); the
+pins reject them, which is the evidence for the readings the oracle takes.
+"""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "lbm_oracle.c")
+
+MUTATIONS = {
+    "fsigma_prefactor_literal_3_2": ("L->w[i] / (2.0 * CS2 * CS2) * contr", "1.5 * L->w[i] * contr"),
+    "force_term_literal_4w_over_rho": ("phi[i] = L->w[i] * cF / CS2;", "phi[i] = 4.0 * L->w[i] * cF / rho;"),
+    "yield_test_literal": ("if (Tn > sqrt2 * rh->sigma_y) {", "if (Tn >= rh->sigma_y) {"),
+    "deviator_literal_full_trace": ("? tr / L->d : 0.0);", "? tr : 0.0);"),
+    "ir_velocity_without_half_force": ("u[a] = (j[a] + 0.5 * F[a]) / rho;", "u[a] = j[a] / rho;"),
+    "strain_rate_missing_factor_2": ("(2.0 * rho * CS2 * tau_prev)", "(rho * CS2 * tau_prev)"),
+    "trt_rates_swapped": ("/ tau_even - (f_asym - e_asym) / tau_odd", "/ tau_odd - (f_asym - e_asym) / tau_even"),
+    "edm_sign": ("fpost[i] = fbar[i] + omega + (feq_shift[i] - feq[i]);",
+                 "fpost[i] = fbar[i] + omega + (feq[i] - feq_shift[i]);"),
+    "bounce_back_without_reversal": ("fbar[i] = dom->P[dom->L.opp[i] * dom->N + n];",
+                                     "fbar[i] = dom->P[i * dom->N + n];"),
+    "streaming_downstream": ("int p[3] = {x - c[0], y - c[1], z - c[2]};",
+                             "int p[3] = {x + c[0], y + c[1], z + c[2]};"),
+    "equilibrium_u2_sign": ("- uu / (2.0 * CS2));", "+ uu / (2.0 * CS2));"),
+    "d3q27_corner_weight": ("wk[3] = 1.0 / 216.0;", "wk[3] = 1.0 / 108.0;"),
+    "interpolation_literal_denominator": ("return nu0 + (gamma / rh->gamma_c) * (nuc - nu0);",
+                                          "return (rh->gamma_c - gamma) / gamma * nu0 + (gamma / rh->gamma_c) * nuc;"),
+    "papanastasiou_sign": ("(rho * gamma) * (-expm1(-rh->m * gamma));", "(rho * gamma) * (expm1(-rh->m * gamma));"),
+    "pr_output_velocity_no_half_force": ("out[3 + a] = u[a] + 0.5 * rh->g[a];", "out[3 + a] = u[a];"),
+    "ir_unyielded_stress_sign": ("sig[a][b] = -Tdev[a][b];", "sig[a][b] = Tdev[a][b];"),
+    "ir_relaxes_full_tensor": ("Tdev[a][b] = T[a][b] - ((a == b && a < L->d) ? tr / L->d : 0.0);",
+                               "Tdev[a][b] = T[a][b];"),
+}
+
+PIN_TESTS = ["tests/test_oracle_lattice.py", "tests/test_oracle_operators.py",
+             "tests/test_oracle_flows.py"]
+
+
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_pins_reject_planted_mistake(name, tmp_path):
+    old, new = MUTATIONS[name]
+    src = open(SRC).read()
+    assert src.count(old) == 1, f"mutation anchor not found once: {old}"
+    mutated = tmp_path / "lbm_oracle.c"
+    mutated.write_text(src.replace(old, new))
+    (tmp_path / "lbm_oracle.h").write_text(open(os.path.join(ROOT, "oracle", "lbm_oracle.h")).read())
+    so = tmp_path / "liboracle_mut.so"
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fno-fast-math",
+                           str(mutated), "-o", str(so), "-lm"])
+    env = dict(os.environ, LBM_ORACLE_LIB=str(so))
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        *PIN_TESTS], cwd=ROOT, env=env, capture_output=True, text=True,
+                       timeout=600)
+    assert r.returncode != 0, f"pins did not catch mutation {name}:\n{r.stdout[-2000:]}"
