@@ -1,0 +1,270 @@
+"""Benchmark of the Bingham-fluid LBM stream-collide library on one GPU.
+
+Main line: D3Q27 periodic 256^3 box of random non-overlapping spheres
+(radius 8, porosity 0.7, SplitMix64 seed 1), implicitly-regularised operator,
+FP64 populations, in-place AA streaming, body force along x, Bingham number
+1 (sigma_y = Bi rho g 2R / 4), started from rest, monitors fused every 100
+steps.  One step = one fused stream-collide launch over the whole domain.
+value = fluid-node updates per second (MLUPS) over the timed steps.
+
+Also reported ("forms"): the PR operator, FP32 and FP16 storage (the FP16
+form on the 384^3 pack, seed 2, with the FP64 fallback near the yield
+surface), the 4x128x128 D3Q19 duct, and the batched duct sweep, each with
+its velocity/flux/plug-volume error against an FP64 run of the same input.
+
+Roofline: algorithmic bytes of the step kernel per launch (fluid nodes x
+2 Q x 8 B, plus 16 B per fluid node of relaxation time for PR) over its
+average duration from HIP events around the timed launches; peak 8 TB/s.
+The CPU baseline is the FP64 oracle (single thread) on one step of the same
+workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "MLUPS and achieved HBM GB/s (% of peak) vs FP64 form at stated velocity error"
+Q = {"D2Q9": 9, "D3Q19": 19, "D3Q27": 27}
+PREC_BYTES = {"FP64": 8, "FP32": 4, "FP16": 2}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes_per_node(lattice, op, precision):
+    """Bytes one fluid-node update must move: read and write every population
+    once, plus read and write the PR relaxation time."""
+    b = 2 * Q[lattice] * PREC_BYTES[precision]
+    if op == "PR":
+        b += 2 * (8 if precision == "FP64" else 4)
+    return b
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1610_01388_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hpp", ".hip")):
+            h.update(open(os.path.join(csrc, name), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def make_domain(lbm, case, precision, scheme="AA", mask=None, **kw):
+    dom = lbm.Domain(case["lattice"], case["dims"], case["periodic"], case["op"], case["nu_p"],
+                     case["sigma_y"], m=case["m"], g=case["g"], precision=precision, scheme=scheme, **kw)
+    if mask is not None:
+        dom.set_mask(mask)
+        dom.init()
+    return dom
+
+
+def timed_run(torch, dom, warmup, steps, mon_every=100):
+    dom.set_monitor_interval(mon_every)
+    dom.step(warmup)
+    torch.cuda.synchronize()
+    stream = dom.stream
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    dom.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    return ms, wall
+
+
+def compare(ref, got, fluid):
+    """Velocity L2-rel, flux rel, plug volume (unyielded count) rel."""
+    rho_r, u_r, _, uy_r = ref
+    rho_g, u_g, _, uy_g = got
+    l2 = float(np.linalg.norm(u_g - u_r) / max(np.linalg.norm(u_r), 1e-300))
+    fr, fg = u_r[0].sum(), u_g[0].sum()
+    flux_rel = float(abs(fg - fr) / max(abs(fr), 1e-300))
+    pr, pg = int(uy_r.sum()), int(uy_g.sum())
+    plug_rel = float(abs(pg - pr) / max(pr, 1))
+    return {"velocity_l2_rel": l2, "flux_rel": flux_rel, "plug_volume_rel": plug_rel,
+            "unyielded_ref": pr, "unyielded": pg}
+
+
+def run_form(torch, lbm, name, case, precision, mask, fluid, warmup, steps, ref=None, **kw):
+    dom = make_domain(lbm, case, precision, mask=mask, **kw)
+    ms, wall = timed_run(torch, dom, warmup, steps)
+    mlups = fluid * steps / (ms * 1e-3) / 1e6
+    bpn = algorithmic_bytes_per_node(case["lattice"], case["op"], precision)
+    gbs = fluid * bpn * steps / (ms * 1e-3) / 1e9
+    out = {"form": name, "lattice": case["lattice"], "operator": case["op"], "precision": precision,
+           "dims": list(case["dims"]), "fluid_nodes": int(fluid), "steps": steps,
+           "ms_per_step": ms / steps, "MLUPS": mlups, "algorithmic_GBs": gbs,
+           "hbm_frac": gbs / HBM_PEAK_GBS, "bytes_per_node": bpn}
+    mom = dom.moments()
+    hist = dom.history()
+    if hist:
+        out["last_monitor"] = {"step": hist[-1]["step"], "flux": float(hist[-1]["flux"][0]),
+                               "fallback_nodes": int(hist[-1]["fallback"]),
+                               "unyielded": int(hist[-1]["unyielded"])}
+    if ref is not None:
+        out["error_vs_fp64"] = compare(ref, mom, fluid)
+    dom.close()
+    torch.cuda.empty_cache()
+    return out, mom
+
+
+def cpu_baseline(case, mask, fluid):
+    """The FP64 oracle (single thread, as it stands) on one step of the
+    same workload."""
+    import oracle
+    op = {"PR": oracle.PR, "IR": oracle.IR}[case["op"]]
+    lat = {"D2Q9": 0, "D3Q19": 1, "D3Q27": 2}[case["lattice"]]
+    rh = oracle.rheology(op, case["nu_p"], case["sigma_y"], case["m"], 1e-8, 0.25, case["g"])
+    od = oracle.Domain(lat, case["dims"], case["periodic"], rh, mask)
+    t0 = time.perf_counter()
+    od.step(1)
+    dt = time.perf_counter() - t0
+    od.close()
+    return {"value": fluid / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": f"1 step of the full {case['dims'][0]}x{case['dims'][1]}x{case['dims'][2]} "
+                      f"{case['lattice']} {case['op']} workload ({fluid} fluid nodes), "
+                      f"{dt:.1f} s single-threaded FP64 C"}
+
+
+def traffic_from_profile(kernel_hash, per_launch_bytes):
+    """HBM traffic of the step kernel from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic_d3q27_ir_fp64_aa_porous256.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except Exception:
+        return None
+    if d.get("kernel_source_hash") != kernel_hash:
+        return None
+    return d.get("traffic_bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--size", type=int, default=256)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-forms", action="store_true", help="main line only")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run a 1 GiB device copy first (counter calibration under rocprofv3)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only; multi-GPU scaling is not part of it "
+              "(see DESIGN.md for how the domain would shard)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1610_01388_amd import inputs, lbm
+    torch.cuda.set_device(0)
+
+    if args.copy_calibration:
+        a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+        torch.cuda.empty_cache()
+
+    n = args.size
+    log(f"generating {n}^3 sphere pack (R=8, porosity 0.7, seed 1)")
+    t0 = time.perf_counter()
+    mask, centres = inputs.sphere_pack((n, n, n), 8.0, 0.7, seed=1)
+    log(f"  {len(centres)} spheres in {time.perf_counter() - t0:.1f} s, porosity {1 - mask.mean():.4f}")
+    fluid = int((mask == 0).sum())
+    case = inputs.porous_case("IR", n=n, Bi=1.0)
+    case_pr = inputs.porous_case("PR", n=n, Bi=1.0, m=1e4)
+
+    log(f"main: D3Q27 {n}^3 IR FP64 AA, warmup {args.warmup}, steps {args.steps}")
+    dom = make_domain(lbm, case, "FP64", mask=mask)
+    tile = dom.tile()
+    ms, wall = timed_run(torch, dom, args.warmup, args.steps)
+    ref_ir = dom.moments()
+    hist = dom.history()
+    dom.close()
+    torch.cuda.empty_cache()
+    ms_step = ms / args.steps
+    mlups = fluid * args.steps / (ms * 1e-3) / 1e6
+    bpn = algorithmic_bytes_per_node("D3Q27", "IR", "FP64")
+    per_launch = fluid * bpn
+    achieved = per_launch / (ms_step * 1e-3) / 1e9
+    khash = kernel_source_hash()
+    traffic = traffic_from_profile(khash, per_launch)
+    log(f"  {ms_step:.3f} ms/step, {mlups:.1f} MLUPS, {achieved:.0f} GB/s algorithmic")
+
+    result = {
+        "metric": METRIC, "value": mlups, "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"D3Q27 periodic {n}^3 random sphere pack (R=8, porosity 0.7, seed 1), "
+                               "IR Bingham operator, Bi=1, FP64, AA in-place streaming",
+                   "lattice": "D3Q27", "operator": "IR", "precision": "FP64", "scheme": "AA",
+                   "dims": [n, n, n], "fluid_nodes": fluid, "porosity": float(1 - mask.mean()),
+                   "nu_p": case["nu_p"], "sigma_y": case["sigma_y"], "g": list(case["g"]),
+                   "tile": list(tile), "monitor_every": 100,
+                   "parity": "velocity L2-rel <= 1e-10 vs the FP64 oracle (tests/test_gpu_parity.py)"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "algorithmic_bytes_per_launch": per_launch, "bytes_per_fluid_node": bpn,
+                     "kernel": "k_step<D3Q27, IR, FP64, AA pull/local>", "kernel_source_hash": khash},
+    }
+    if hist:
+        result["config"]["last_monitor"] = {"step": hist[-1]["step"], "flux": float(hist[-1]["flux"][0]),
+                                            "mass": hist[-1]["mass"], "umax": hist[-1]["umax"],
+                                            "unyielded": int(hist[-1]["unyielded"])}
+
+    forms = []
+    if not args.no_forms:
+        W, K = args.warmup, min(args.steps, 500)
+        ref_steps_ir = None
+        # FP64 references at W+K steps for the error statements
+        log("forms: FP64 references")
+        f64_ir, ref_ir = run_form(torch, lbm, "IR FP64", case, "FP64", mask, fluid, W, K)
+        f64_pr, ref_pr = run_form(torch, lbm, "PR FP64", case_pr, "FP64", mask, fluid, W, K)
+        forms += [f64_ir, f64_pr]
+        log("forms: FP32")
+        forms.append(run_form(torch, lbm, "IR FP32", case, "FP32", mask, fluid, W, K, ref=ref_ir)[0])
+        forms.append(run_form(torch, lbm, "PR FP32", case_pr, "FP32", mask, fluid, W, K, ref=ref_pr)[0])
+        log("forms: FP16 storage with FP64 fallback")
+        forms.append(run_form(torch, lbm, "IR FP16+fallback", case, "FP16", mask, fluid, W, K, ref=ref_ir,
+                              fp64_fallback=True, fallback_band=0.05, fp16_scale_log2=14)[0])
+        forms.append(run_form(torch, lbm, "PR FP16+fallback", case_pr, "FP16", mask, fluid, W, K, ref=ref_pr,
+                              fp64_fallback=True, fallback_band=1.0, fp16_scale_log2=14)[0])
+        del ref_ir, ref_pr
+        log("forms: D3Q19 4x128x128 duct (cache-resident: MLUPS only)")
+        duct = inputs.duct_case("IR", side=128, length=4, Bi=0.5)
+        dfl = 128 * 128 * 4
+        d64, dref = run_form(torch, lbm, "duct D3Q19 IR FP64", duct, "FP64", None, dfl, W, K)
+        d32, _ = run_form(torch, lbm, "duct D3Q19 IR FP32", duct, "FP32", None, dfl, W, K, ref=dref)
+        forms += [d64, d32]
+    result["forms"] = forms
+
+    if not args.no_cpu:
+        log("cpu baseline: oracle, one step of the main workload")
+        result["cpu_baseline"] = cpu_baseline(case, mask, fluid)
+    else:
+        result["cpu_baseline"] = None
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

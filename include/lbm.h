@@ -1,0 +1,207 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) lattice Boltzmann library for
+ * Bingham (yield-stress) fluids: fused stream-collide with the
+ * Papanastasiou-regularised (PR) and implicitly-regularised (IR) operators of
+ * Regulski, Leonardi & Szumbarski, "On the spatial convergence and transient
+ * behaviour of lattice Boltzmann methods for modelling fluids with yield
+ * stress" (arXiv:1610.01388).
+ *
+ * General rules
+ *   - Every function is extern "C", never throws and never aborts; it
+ *     returns LBM_OK (0) or a negative lbm_status.  lbm_last_error() gives a
+ *     message for the last failure on the calling thread.
+ *   - Device memory is allocated by the caller and bound by pointer
+ *     (lbm_bind); the library never allocates or frees device memory.
+ *     Sizes come from lbm_query_sizes.  Host buffers are caller-owned.
+ *   - All device work is enqueued on the stream given to lbm_bind, in order.
+ *     Functions that return host data synchronise that stream.
+ *   - Node index n = x + nx*(y + ny*z) (x fastest).  Populations are
+ *     indexed [i][n] in the library's velocity order (lbm_lattice_info).
+ *   - A domain is used by one host thread at a time.
+ *
+ * Model (what one step computes, for every fluid node x)
+ *   1. streaming (Sec. 2, Eq. 10): f_i(x) = f_i^post(x - c_i), with halfway
+ *      bounce-back f_i(x) = f_opp(i)^post(x) where x - c_i is solid or lies
+ *      beyond a wall face (Sec. 4.3); periodic axes wrap;
+ *   2. moments rho, j, Pi (Eq. 9) of the transformed populations (Eq. 11);
+ *   3. PR: strain rate from the non-equilibrium second moment with the
+ *      previous step's relaxation time (Sec. 2.2 Eq. 24, Sec. 3), apparent
+ *      viscosity of Eqs. 36-37 with the cut-off gamma_c, TRT collision with
+ *      magic number Lambda (Sec. 2.1) and EDM body force (Sec. 2.4 Eq. 34);
+ *      IR: stress solve of Sec. 3.2 (Eqs. 31, 38-40) and post-collision
+ *      populations of Sec. 2.3 (Eqs. 28-29) with the force term of Eq. 35;
+ *   4. store the post-collision populations (and PR's relaxation time).
+ *   The reported velocity is j/rho + g/2 for both operators.
+ *   Walls of non-periodic axes sit half a node outside the first and last
+ *   node; solid nodes (mask byte 1) are never updated.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LBM_OK = 0,
+    LBM_EINVAL = -1,    /* invalid argument or descriptor                    */
+    LBM_ENOMEM = -2,    /* a bound buffer is smaller than required           */
+    LBM_EHIP = -3,      /* a HIP runtime call failed                         */
+    LBM_ESTATE = -4,    /* call out of order (e.g. step before bind)         */
+    LBM_EUNSTABLE = -5, /* monitors found non-finite values or |u| > umax    */
+    LBM_EFORMAT = -6    /* checkpoint blob malformed or for another domain   */
+} lbm_status;
+
+typedef enum { LBM_D2Q9 = 0, LBM_D3Q19 = 1, LBM_D3Q27 = 2 } lbm_lattice;
+typedef enum { LBM_PR = 0, LBM_IR = 1 } lbm_operator;
+/* Storage of the populations.  All three store deviations h_i = f_i - w_i
+ * rho0.  FP64: h in double, collision in double.  FP32: h in float,
+ * collision in float.  FP16: h_i * 2^k / w_i in IEEE half (k =
+ * fp16_scale_log2, round to nearest even), collision in float. */
+typedef enum { LBM_FP64 = 0, LBM_FP32 = 1, LBM_FP16 = 2 } lbm_precision;
+/* A/B: two population copies, pull streaming.  AA: one copy, streaming
+ * folded into alternate steps (in place). */
+typedef enum { LBM_AB = 0, LBM_AA = 1 } lbm_scheme;
+/* COMPACT: population slots for fluid nodes only (numbered in node order),
+ * solid mask held as one bitmap per (y, z) row; the step reads and writes
+ * fluid data only.  DENSE: a slot for every node, one mask byte per node
+ * staged in LDS tiles.  Both give identical results. */
+typedef enum { LBM_COMPACT = 0, LBM_DENSE = 1 } lbm_layout;
+
+typedef struct {
+    int32_t lattice;     /* lbm_lattice                                      */
+    int32_t nx, ny, nz;  /* nodes per axis; nz must be 1 for D2Q9            */
+    int32_t periodic[3]; /* nonzero: periodic axis; 0: bounce-back walls     */
+    int32_t precision;   /* lbm_precision                                    */
+    int32_t scheme;      /* lbm_scheme                                       */
+    int32_t layout;      /* lbm_layout                                       */
+} lbm_desc;
+
+typedef struct {
+    int32_t op;              /* lbm_operator                                  */
+    int32_t fp64_fallback;   /* FP32/FP16: redo near-yield nodes in FP64      */
+    double nu_p;             /* plastic kinematic viscosity (> 0)             */
+    double sigma_y;          /* yield stress per unit density (>= 0)          */
+    double rho0;             /* reference density (> 0), usually 1            */
+    double m;                /* PR: Papanastasiou parameter (>= 0)            */
+    double gamma_c;          /* PR: strain-rate cut-off (> 0), e.g. 1e-8      */
+    double lambda_trt;       /* PR: TRT magic number (> 0), e.g. 0.25         */
+    double g[3];             /* body force per unit mass                      */
+    double fallback_band;    /* IR: |T/(sqrt2 sigma_y) - 1| < band; PR:
+                                m*gamma_dot < band -> node done in FP64      */
+    int32_t fp16_scale_log2; /* FP16: k in h*2^k/w (0..24), e.g. 14           */
+    int32_t reserved;
+} lbm_rheology;
+
+typedef struct {
+    int64_t step;           /* time of the record (collisions done)           */
+    double flux[3];         /* sum of velocity over fluid nodes / all nodes   */
+    double mass;            /* sum of rho over fluid nodes                    */
+    double umax;            /* max |u| over fluid nodes                       */
+    int64_t fluid_nodes;
+    int64_t unyielded;      /* IR: T <= sqrt2 sigma_y; PR: rho nu_app gamma_dot < sigma_y */
+    int64_t fallback_nodes; /* nodes recomputed in FP64 (reduced precision)   */
+    int64_t nonfinite;      /* fluid nodes with a non-finite rho or u         */
+} lbm_monitor;
+
+typedef struct {
+    size_t pdf_bytes;   /* population storage (x2 for A/B)                  */
+    size_t tau_bytes;   /* PR relaxation-time field (0 for IR)             */
+    size_t mask_bytes;  /* uint8 per node                                  */
+    size_t work_bytes;  /* monitor partials, history ring, IO staging      */
+} lbm_sizes;
+
+typedef struct lbm_domain lbm_domain;
+
+/* Message for the last error on this thread ("" if none). */
+const char* lbm_last_error(void);
+
+/* Library velocity order: c (3*q ints), w (q doubles), opp (q ints); any
+ * pointer may be NULL.  *q receives the velocity count. */
+int lbm_lattice_info(int32_t lattice, int32_t* q, int32_t* c, double* w, int32_t* opp);
+
+/* Bytes of each device buffer the caller must bind for this descriptor. */
+int lbm_query_sizes(const lbm_desc* desc, const lbm_rheology* rh, lbm_sizes* out);
+
+/* Validate and create a domain.  Errors (LBM_EINVAL): unknown lattice,
+ * precision or scheme; non-positive sizes; nz != 1 for D2Q9; nu_p <= 0;
+ * sigma_y < 0; rho0 <= 0; PR with m < 0, gamma_c <= 0 or lambda_trt <= 0;
+ * fp16_scale_log2 outside 0..24; fallback_band < 0. */
+int lbm_create(const lbm_desc* desc, const lbm_rheology* rh, lbm_domain** out);
+
+/* Bind caller-owned device buffers (sizes from lbm_query_sizes; tau may be
+ * NULL for IR) and the HIP stream (hipStream_t, NULL = default stream).
+ * The mask buffer is cleared to all-fluid and the populations are set to
+ * rest at rho0 (lbm_init_equilibrium(rho0, 0)). */
+int lbm_bind(lbm_domain* dom, void* pdf_dev, void* tau_dev, void* mask_dev, void* work_dev,
+             void* hip_stream);
+
+/* Set the solid mask from a host array (N bytes, 1 = solid, 0 = fluid) and
+ * reset the state to rest (lbm_init_equilibrium(rho0, 0)): the compact
+ * layout renumbers the population slots.  Synchronises. */
+int lbm_set_mask(lbm_domain* dom, const uint8_t* host_mask);
+
+/* Post-collision state f_eq(rho0, u0) at every fluid node, time 0; PR
+ * relaxation time set to the zero-strain value 1/2 + 3 (nu_p + m sigma_y/rho0)
+ * (Sec. 4.4 start from rest: u0 = 0). */
+int lbm_init_equilibrium(lbm_domain* dom, double rho0, const double* u0);
+
+/* Set / get the post-collision populations of the last step (q*N doubles,
+ * [i][n], library order, full f_i -- not deviations) and, for PR, the
+ * relaxation-time field (N doubles; may be NULL).  Writing converts to the
+ * storage precision.  Both synchronise. */
+int lbm_write_populations(lbm_domain* dom, const double* host_P, const double* host_tau);
+int lbm_read_populations(lbm_domain* dom, double* host_P, double* host_tau);
+
+/* Enqueue nsteps time steps (asynchronous). */
+int lbm_step(lbm_domain* dom, int64_t nsteps);
+
+/* Current time (number of collisions done). */
+int lbm_time(lbm_domain* dom, int64_t* t);
+
+/* Fuse monitors into every k-th step (0 = off).  Each record (lbm_monitor of
+ * the state the step starts from) goes to a device ring of 4096 records;
+ * lbm_read_history copies out the records produced since the last call
+ * (oldest first, at most max) and synchronises. */
+int lbm_set_monitor_interval(lbm_domain* dom, int32_t k);
+int lbm_read_history(lbm_domain* dom, lbm_monitor* out, int32_t max, int32_t* count);
+
+/* Monitors of the current state; synchronises.  Returns LBM_EUNSTABLE (with
+ * *out filled) when a fluid node is non-finite or umax exceeds the limit set
+ * by lbm_set_umax_limit (default 0.1, the Mach validity bound of Sec. 4.5.3). */
+int lbm_monitors(lbm_domain* dom, lbm_monitor* out);
+int lbm_set_umax_limit(lbm_domain* dom, double umax);
+
+/* Moments of the current state into host buffers (N doubles rho, 3*N
+ * doubles u component-major u[a*N+n], N doubles nu_app (PR; IR reports
+ * nu_p), N bytes unyielded flag).  Any pointer may be NULL.  Solid nodes
+ * report zeros.  Synchronises. */
+int lbm_read_moments(lbm_domain* dom, double* rho, double* u, double* nu_app,
+                     uint8_t* unyielded);
+
+/* Checkpoint: the blob holds a header (descriptor, rheology, time, scheme
+ * phase), the raw population storage, the PR field and the mask.  With
+ * blob == NULL, lbm_save only reports the size in *bytes.  lbm_load rejects
+ * (LBM_EFORMAT) a blob that is truncated or was saved from a domain with a
+ * different descriptor.  Both synchronise. */
+int lbm_save(lbm_domain* dom, void* blob, size_t* bytes);
+int lbm_load(lbm_domain* dom, const void* blob, size_t bytes);
+
+/* Tile shape of the step kernel: one node per thread, tx*ty*tz threads per
+ * block, which must be 64, 128, 192 or 256; tz must be 1 for D2Q9; the
+ * compact layout needs tx == 64 (one wavefront per 64-node row segment). */
+int lbm_set_tile(lbm_domain* dom, int32_t tx, int32_t ty, int32_t tz);
+int lbm_get_tile(lbm_domain* dom, int32_t* tx, int32_t* ty, int32_t* tz);
+/* Time candidate tile shapes on the bound buffers (the state is saved and
+ * restored around the trial steps) and keep the fastest; synchronises. */
+int lbm_autotune(lbm_domain* dom, int32_t trial_steps);
+
+int lbm_destroy(lbm_domain* dom);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

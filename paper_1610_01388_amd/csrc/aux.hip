@@ -1,0 +1,399 @@
+// aux.hip -- node-range kernels around the step: initial state, moments
+// readout, monitors on demand, population read/write, and the deterministic
+// finalisation of monitor partial sums.  None of these is on the hot loop;
+// they favour plain 1-D indexing over tiling.
+#include <type_traits>
+
+#include "device_common.hpp"
+
+namespace lbm {
+
+template <int LAT>
+hipError_t launch_step_lattice(int op, int prec, int pat, bool mon, int layout, const StepArgs& a, hipStream_t s);
+
+// Layout of the stored state (NodeArgs::layout):
+//  0: post-collision, natural slots  (A/B; slot i at x holds P_i(x))
+//  1: post-collision, swapped slots  (AA after an even number of steps;
+//     slot opp(i) at x holds P_i(x))
+//  2: streamed, natural slots        (AA after an odd number of steps; slot
+//     i at x holds P_i(x - c_i), or P_opp(i)(x) behind a solid / wall)
+enum { LAY_POST = 0, LAY_POST_SWAPPED = 1, LAY_STREAMED = 2 };
+
+__device__ __forceinline__ void node_xyz(int64_t n, int nx, int ny, int& x, int& y, int& z)
+{
+    x = (int)(n % nx);
+    const int64_t r = n / nx;
+    y = (int)(r % ny);
+    z = (int)(r / ny);
+}
+
+// Population slot of node (x, y, z) (inside the box), or -1 if it is solid.
+__device__ __forceinline__ int64_t slot_of(const NodeArgs& a, int x, int y, int z)
+{
+    if (a.compact) {
+        const int64_t row = ((int64_t)y + (int64_t)a.ny * z) * a.W + (x >> 6);
+        const uint64_t word = a.bits[row];
+        if (!((word >> (x & 63)) & 1)) return -1;
+        return (int64_t)a.wbase[row] + __popcll(word & ((1ull << (x & 63)) - 1ull));
+    }
+    const int64_t n = x + (int64_t)a.nx * (y + (int64_t)a.ny * z);
+    return a.mask[n] ? -1 : n;
+}
+
+// Slot of the neighbour at (x,y,z) + c, or -1 when it is solid or lies
+// beyond a wall face; periodic axes wrap.
+__device__ __forceinline__ int64_t neighbour(const NodeArgs& a, int x, int y, int z, int cx, int cy, int cz)
+{
+    int p[3] = {x + cx, y + cy, z + cz};
+    const int n3[3] = {a.nx, a.ny, a.nz};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        if (p[k] < 0 || p[k] >= n3[k]) {
+            if (!a.per[k]) return -1;
+            p[k] = (p[k] + n3[k]) % n3[k];
+        }
+    }
+    return slot_of(a, p[0], p[1], p[2]);
+}
+
+template <class C> __device__ __forceinline__ const Coll<C>& ncoll(const NodeArgs& a);
+template <> __device__ __forceinline__ const Coll<double>& ncoll<double>(const NodeArgs& a) { return a.cd; }
+template <> __device__ __forceinline__ const Coll<float>& ncoll<float>(const NodeArgs& a) { return a.cf; }
+
+// Pre-collision populations (deviations) the next step would see at the
+// fluid node (x, y, z) with slot k.
+template <int LAT, int PREC>
+__device__ __forceinline__ void gather(const NodeArgs& a, int64_t k, int x, int y, int z,
+                                       typename Store<PREC>::C (&h)[Lattice<LAT>::Q])
+{
+    using L = Lattice<LAT>;
+    using S = typename Store<PREC>::S;
+    const S* A = (const S*)a.pdf;
+    const int64_t St = a.S;
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        int64_t idx;
+        if (a.layout == LAY_STREAMED) {
+            idx = (int64_t)i * St + k;
+        } else {
+            const int64_t src = neighbour(a, x, y, z, -L::cx[i], -L::cy[i], -L::cz[i]);
+            if (a.layout == LAY_POST)
+                idx = src >= 0 ? (int64_t)i * St + src : (int64_t)opp(i) * St + k;
+            else
+                idx = src >= 0 ? (int64_t)opp(i) * St + src : (int64_t)i * St + k;
+        }
+        h[i] = decode<PREC>(A[idx], L::w[i], a.h16_scale);
+    }
+}
+
+// Readout of the current state: per-node moments into staging
+// (out[0..count) rho, out[count..4count) u component-major, out[4count..5count)
+// nu_app; out_flags unyielded), or per-block monitor partials.
+template <int LAT, int OP, int PREC>
+__global__ __launch_bounds__(256) void k_readout(const NodeArgs a)
+{
+    using L = Lattice<LAT>;
+    using C = typename Store<PREC>::C;
+    using T = typename Store<PREC>::T;
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t n = a.n0 + j;
+    const bool inside = j < a.count;
+    int x = 0, y = 0, z = 0;
+    int64_t k = -1;
+    if (inside) {
+        node_xyz(n, a.nx, a.ny, x, y, z);
+        k = slot_of(a, x, y, z);
+    }
+    const bool active = k >= 0;
+    const Coll<C>& cp = ncoll<C>(a);
+    Moments<C> mo;
+    Pre<C> pr;
+    C uo[3] = {C(0), C(0), C(0)};
+    if (active) {
+        C h[L::Q];
+        gather<LAT, PREC>(a, k, x, y, z, h);
+        const C tau_prev = (OP == OP_PR) ? (C)((const T*)a.tau)[k] : C(0);
+        mo = moments<LAT>(h);
+        pr = rheology<LAT, OP>(mo, cp, tau_prev);
+        out_velocity(mo, pr, cp, uo);
+    }
+    if (a.reduce) {
+        double v[MP_COUNT];
+#pragma unroll
+        for (int q = 0; q < MP_COUNT; ++q) v[q] = 0.0;
+        if (active) {
+            const double ux = uo[0], uy = uo[1], uz = uo[2], rho = pr.rho;
+            const bool bad = !isfinite(rho) || !isfinite(ux) || !isfinite(uy) || !isfinite(uz);
+            v[MP_UX] = ux;
+            v[MP_UY] = uy;
+            v[MP_UZ] = uz;
+            v[MP_MASS] = rho;
+            v[MP_UMAX] = bad ? INFINITY : sqrt(ux * ux + uy * uy + uz * uz);
+            v[MP_UNYIELDED] = pr.unyielded ? 1.0 : 0.0;
+            v[MP_NONFINITE] = bad ? 1.0 : 0.0;
+            v[MP_FLUID] = 1.0;
+        }
+        block_reduce_store<MP_COUNT>(v, a.partials + (int64_t)blockIdx.x * MP_COUNT);
+        return;
+    }
+    if (!inside) return;
+    const int64_t c = a.count;
+    a.out[j] = active ? (double)pr.rho : 0.0;
+    a.out[c + j] = active ? (double)uo[0] : 0.0;
+    a.out[2 * c + j] = active ? (double)uo[1] : 0.0;
+    a.out[3 * c + j] = active ? (double)uo[2] : 0.0;
+    a.out[4 * c + j] = active ? (double)pr.nu_app : 0.0;
+    a.out_flags[j] = active ? (uint8_t)pr.unyielded : (uint8_t)0;
+}
+
+// Equilibrium f_eq(rho, u0) (Sec. 2.1, Eq. 12) as the post-collision state;
+// stored as deviations from w rho0, in the layout given (0 or 1).  Dense
+// storage also clears the slots of solid nodes.
+template <int LAT, int OP, int PREC>
+__global__ __launch_bounds__(256) void k_init(const NodeArgs a, double rho)
+{
+    using L = Lattice<LAT>;
+    using S = typename Store<PREC>::S;
+    using T = typename Store<PREC>::T;
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= a.N) return;
+    int x, y, z;
+    node_xyz(n, a.nx, a.ny, x, y, z);
+    int64_t k = slot_of(a, x, y, z);
+    const bool solid = k < 0;
+    if (solid) {
+        if (a.compact) return;
+        k = n;
+    }
+    S* A = (S*)a.pdf;
+    const double u0[3] = {a.u0[0], a.u0[1], a.u0[2]};
+    const double uu = u0[0] * u0[0] + u0[1] * u0[1] + u0[2] * u0[2];
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        const double cu = L::cx[i] * u0[0] + L::cy[i] * u0[1] + L::cz[i] * u0[2];
+        const double feq = rho * L::w[i] * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+        const double hdev = solid ? 0.0 : feq - L::w[i] * a.cd.rho0;
+        const int slot = (a.layout == LAY_POST_SWAPPED) ? opp(i) : i;
+        A[(int64_t)slot * a.S + k] = encode<PREC>((typename Store<PREC>::C)hdev, L::w[i], a.h16_inv);
+    }
+    if (OP == OP_PR && a.tau) {
+        const double nu0 = a.cd.nu_p + a.cd.m * a.cd.sigma_y / rho;
+        ((T*)a.tau)[k] = (T)(0.5 + 3.0 * nu0);
+    }
+}
+
+// Write full populations P (staging: q blocks of count doubles, node order)
+// and tau into storage in layout 0 or 1.  Solid nodes carry no state.
+template <int LAT, int PREC>
+__global__ __launch_bounds__(256) void k_pop_write(const NodeArgs a)
+{
+    using L = Lattice<LAT>;
+    using S = typename Store<PREC>::S;
+    using T = typename Store<PREC>::T;
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= a.count) return;
+    const int64_t n = a.n0 + j;
+    int x, y, z;
+    node_xyz(n, a.nx, a.ny, x, y, z);
+    const int64_t k = slot_of(a, x, y, z);
+    if (k < 0) return;
+    S* A = (S*)a.pdf;
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        const double hdev = a.out[(int64_t)i * a.count + j] - L::w[i] * a.cd.rho0;
+        const int slot = (a.layout == LAY_POST_SWAPPED) ? opp(i) : i;
+        A[(int64_t)slot * a.S + k] = encode<PREC>((typename Store<PREC>::C)hdev, L::w[i], a.h16_inv);
+    }
+    if (a.tau) ((T*)a.tau)[k] = (T)a.out[(int64_t)L::Q * a.count + j];
+}
+
+// Read the post-collision populations P of the last step (full f) and tau
+// in node order (solid nodes report 0).  Layout 2 undoes the push of the
+// last AA step: P_i(x) sits in slot i of x + c_i, or in slot opp(i) of x when
+// x + c_i is solid or beyond a wall.
+template <int LAT, int PREC>
+__global__ __launch_bounds__(256) void k_pop_read(const NodeArgs a)
+{
+    using L = Lattice<LAT>;
+    using S = typename Store<PREC>::S;
+    using T = typename Store<PREC>::T;
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= a.count) return;
+    const int64_t n = a.n0 + j;
+    const S* A = (const S*)a.pdf;
+    int x, y, z;
+    node_xyz(n, a.nx, a.ny, x, y, z);
+    const int64_t k = slot_of(a, x, y, z);
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        double v = 0.0;
+        if (k >= 0) {
+            int64_t idx;
+            if (a.layout == LAY_POST) {
+                idx = (int64_t)i * a.S + k;
+            } else if (a.layout == LAY_POST_SWAPPED) {
+                idx = (int64_t)opp(i) * a.S + k;
+            } else {
+                const int64_t dst = neighbour(a, x, y, z, L::cx[i], L::cy[i], L::cz[i]);
+                idx = dst >= 0 ? (int64_t)i * a.S + dst : (int64_t)opp(i) * a.S + k;
+            }
+            v = (double)decode<PREC>(A[idx], L::w[i], a.h16_scale) + L::w[i] * a.cd.rho0;
+        }
+        a.out[(int64_t)i * a.count + j] = v;
+    }
+    if (a.tau) a.out[(int64_t)L::Q * a.count + j] = k >= 0 ? (double)((const T*)a.tau)[k] : 0.0;
+}
+
+// Sum per-block partials in a fixed order into one lbm_monitor record.
+struct MonitorRecord {
+    int64_t step;
+    double flux[3];
+    double mass;
+    double umax;
+    int64_t fluid_nodes, unyielded, fallback_nodes, nonfinite;
+};
+
+__global__ __launch_bounds__(256) void k_finalize(const double* parts, int64_t np, MonitorRecord* rec,
+                                                  int64_t step, double ntotal)
+{
+    __shared__ double red[256][MP_COUNT];
+    double v[MP_COUNT];
+#pragma unroll
+    for (int k = 0; k < MP_COUNT; ++k) v[k] = 0.0;
+    for (int64_t j = threadIdx.x; j < np; j += 256) {
+#pragma unroll
+        for (int k = 0; k < MP_COUNT; ++k) {
+            const double o = parts[j * MP_COUNT + k];
+            v[k] = (k == MP_UMAX) ? fmax(v[k], o) : v[k] + o;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < MP_COUNT; ++k) red[threadIdx.x][k] = v[k];
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+#pragma unroll
+            for (int k = 0; k < MP_COUNT; ++k)
+                red[threadIdx.x][k] = (k == MP_UMAX) ? fmax(red[threadIdx.x][k], red[threadIdx.x + s][k])
+                                                     : red[threadIdx.x][k] + red[threadIdx.x + s][k];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        rec->step = step;
+        rec->flux[0] = red[0][MP_UX] / ntotal;
+        rec->flux[1] = red[0][MP_UY] / ntotal;
+        rec->flux[2] = red[0][MP_UZ] / ntotal;
+        rec->mass = red[0][MP_MASS];
+        rec->umax = red[0][MP_UMAX];
+        rec->fluid_nodes = (int64_t)red[0][MP_FLUID];
+        rec->unyielded = (int64_t)red[0][MP_UNYIELDED];
+        rec->fallback_nodes = (int64_t)red[0][MP_FALLBACK];
+        rec->nonfinite = (int64_t)red[0][MP_NONFINITE];
+    }
+}
+
+__global__ void k_fill_u8(uint8_t* p, int64_t n, uint8_t v)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) p[k] = v;
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+template <int V> using ic = std::integral_constant<int, V>;
+
+// Call f(ic<LAT>, ic<PREC>) for runtime lattice and precision.
+template <class F>
+static hipError_t dispatch_lat_prec(int lat, int prec, F&& f)
+{
+    switch (lat * 3 + prec) {
+    case 0: return f(ic<0>{}, ic<0>{});
+    case 1: return f(ic<0>{}, ic<1>{});
+    case 2: return f(ic<0>{}, ic<2>{});
+    case 3: return f(ic<1>{}, ic<0>{});
+    case 4: return f(ic<1>{}, ic<1>{});
+    case 5: return f(ic<1>{}, ic<2>{});
+    case 6: return f(ic<2>{}, ic<0>{});
+    case 7: return f(ic<2>{}, ic<1>{});
+    case 8: return f(ic<2>{}, ic<2>{});
+    default: return hipErrorInvalidValue;
+    }
+}
+
+static inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+hipError_t launch_readout(int lat, int op, int prec, const NodeArgs& a, hipStream_t s, int64_t* nblocks)
+{
+    if (nblocks) *nblocks = (int64_t)nblk(a.count);
+    if (a.count == 0) return hipSuccess;
+    return dispatch_lat_prec(lat, prec, [&](auto L, auto P) {
+        if (op == OP_PR)
+            hipLaunchKernelGGL((k_readout<decltype(L)::value, OP_PR, decltype(P)::value>), dim3(nblk(a.count)),
+                               dim3(256), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_readout<decltype(L)::value, OP_IR, decltype(P)::value>), dim3(nblk(a.count)),
+                               dim3(256), 0, s, a);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_init(int lat, int op, int prec, const NodeArgs& a, double rho, hipStream_t s)
+{
+    return dispatch_lat_prec(lat, prec, [&](auto L, auto P) {
+        if (op == OP_PR)
+            hipLaunchKernelGGL((k_init<decltype(L)::value, OP_PR, decltype(P)::value>), dim3(nblk(a.N)), dim3(256),
+                               0, s, a, rho);
+        else
+            hipLaunchKernelGGL((k_init<decltype(L)::value, OP_IR, decltype(P)::value>), dim3(nblk(a.N)), dim3(256),
+                               0, s, a, rho);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_pop_write(int lat, int prec, const NodeArgs& a, hipStream_t s)
+{
+    if (a.count == 0) return hipSuccess;
+    return dispatch_lat_prec(lat, prec, [&](auto L, auto P) {
+        hipLaunchKernelGGL((k_pop_write<decltype(L)::value, decltype(P)::value>), dim3(nblk(a.count)), dim3(256), 0,
+                           s, a);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_pop_read(int lat, int prec, const NodeArgs& a, hipStream_t s)
+{
+    if (a.count == 0) return hipSuccess;
+    return dispatch_lat_prec(lat, prec, [&](auto L, auto P) {
+        hipLaunchKernelGGL((k_pop_read<decltype(L)::value, decltype(P)::value>), dim3(nblk(a.count)), dim3(256), 0,
+                           s, a);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_finalize(const double* partials, int64_t nparts, void* record, int64_t step, double ntotal,
+                           hipStream_t s)
+{
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, partials, nparts, (MonitorRecord*)record, step, ntotal);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u8(uint8_t* p, int64_t n, uint8_t v, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u8, dim3(nblk(n)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_step(int lat, int op, int prec, int pat, bool mon, int layout, const StepArgs& a, hipStream_t s)
+{
+    switch (lat) {
+    case 0: return launch_step_lattice<0>(op, prec, pat, mon, layout, a, s);
+    case 1: return launch_step_lattice<1>(op, prec, pat, mon, layout, a, s);
+    case 2: return launch_step_lattice<2>(op, prec, pat, mon, layout, a, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace lbm

@@ -1,0 +1,830 @@
+// capi.hip -- host side of the C ABI declared in include/lbm.h: validation,
+// buffer binding, the step loop (A/B copy swap or AA phase alternation),
+// fused monitors, chunked host I/O through a staging area, checkpoints and
+// the tile autotuner.  The library never allocates device memory: every
+// device buffer is bound by the caller.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+#include "lbm.h"
+
+using namespace lbm;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                            \
+    do {                                                                                        \
+        hipError_t e_ = (expr);                                                                 \
+        if (e_ != hipSuccess) return fail(LBM_EHIP, "%s: %s", #expr, hipGetErrorString(e_));    \
+    } while (0)
+
+constexpr int kHistory = 4096;
+constexpr size_t kStageMax = size_t(64) << 20;
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct MonitorRecord {
+    int64_t step;
+    double flux[3];
+    double mass;
+    double umax;
+    int64_t fluid_nodes, unyielded, fallback_nodes, nonfinite;
+};
+static_assert(sizeof(MonitorRecord) == sizeof(lbm_monitor), "record layout must match lbm_monitor");
+static_assert((int)LAYOUT_COMPACT == (int)LBM_COMPACT && (int)LAYOUT_DENSE == (int)LBM_DENSE,
+              "kernel layout codes must equal the C ABI's lbm_layout values");
+static_assert((int)PREC_F64 == (int)LBM_FP64 && (int)PREC_F32 == (int)LBM_FP32 && (int)PREC_F16 == (int)LBM_FP16,
+              "kernel precision codes must equal the C ABI's lbm_precision values");
+static_assert((int)OP_PR == (int)LBM_PR && (int)OP_IR == (int)LBM_IR,
+              "kernel operator codes must equal the C ABI's lbm_operator values");
+
+int lattice_q(int lat) { return lat == 0 ? 9 : lat == 1 ? 19 : lat == 2 ? 27 : -1; }
+int lattice_d(int lat) { return lat == 0 ? 2 : 3; }
+size_t prec_bytes(int p) { return p == LBM_FP64 ? 8 : p == LBM_FP32 ? 4 : 2; }
+
+struct Layout {
+    size_t pdf_copy, pdf, tau, mask, part, hist, rec, stage, work;
+    size_t bits_off, base_off, mask_compact;  // compact mask: bitmap then word bases
+    int64_t max_parts, npad;
+    int W;
+};
+
+int check_desc(const lbm_desc* d)
+{
+    if (!d) return fail(LBM_EINVAL, "descriptor is NULL");
+    if (lattice_q(d->lattice) < 0) return fail(LBM_EINVAL, "unknown lattice %d", d->lattice);
+    if (d->nx < 1 || d->ny < 1 || d->nz < 1) return fail(LBM_EINVAL, "non-positive size %dx%dx%d", d->nx, d->ny, d->nz);
+    if (d->lattice == LBM_D2Q9 && d->nz != 1) return fail(LBM_EINVAL, "D2Q9 needs nz == 1");
+    if ((int64_t)d->nx * d->ny * d->nz > (int64_t)1 << 36) return fail(LBM_EINVAL, "domain too large");
+    if (d->precision < LBM_FP64 || d->precision > LBM_FP16) return fail(LBM_EINVAL, "unknown precision %d", d->precision);
+    if (d->scheme != LBM_AB && d->scheme != LBM_AA) return fail(LBM_EINVAL, "unknown scheme %d", d->scheme);
+    if (d->layout != LBM_COMPACT && d->layout != LBM_DENSE) return fail(LBM_EINVAL, "unknown layout %d", d->layout);
+    return LBM_OK;
+}
+
+int check_rheology(const lbm_rheology* r)
+{
+    if (!r) return fail(LBM_EINVAL, "rheology is NULL");
+    if (r->op != LBM_PR && r->op != LBM_IR) return fail(LBM_EINVAL, "unknown operator %d", r->op);
+    if (!(r->nu_p > 0)) return fail(LBM_EINVAL, "nu_p must be > 0 (tau > 1/2)");
+    if (!(r->sigma_y >= 0)) return fail(LBM_EINVAL, "sigma_y must be >= 0");
+    if (!(r->rho0 > 0)) return fail(LBM_EINVAL, "rho0 must be > 0");
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(r->g[a])) return fail(LBM_EINVAL, "body force must be finite");
+    if (r->op == LBM_PR) {
+        if (!(r->m >= 0)) return fail(LBM_EINVAL, "m must be >= 0");
+        if (!(r->gamma_c > 0)) return fail(LBM_EINVAL, "gamma_c must be > 0");
+        if (!(r->lambda_trt > 0)) return fail(LBM_EINVAL, "lambda_trt must be > 0");
+    }
+    if (r->fp16_scale_log2 < 0 || r->fp16_scale_log2 > 24) return fail(LBM_EINVAL, "fp16_scale_log2 outside 0..24");
+    if (!(r->fallback_band >= 0)) return fail(LBM_EINVAL, "fallback_band must be >= 0");
+    return LBM_OK;
+}
+
+Layout layout_of(const lbm_desc* d, const lbm_rheology* r)
+{
+    Layout L{};
+    const int64_t N = (int64_t)d->nx * d->ny * d->nz;
+    const int Q = lattice_q(d->lattice);
+    L.npad = (N + 63) / 64 * 64;
+    L.pdf_copy = align_up((size_t)Q * L.npad * prec_bytes(d->precision));
+    L.pdf = L.pdf_copy * (d->scheme == LBM_AB ? 2 : 1);
+    L.tau = (r && r->op == LBM_PR) ? align_up((size_t)L.npad * (d->precision == LBM_FP64 ? 8 : 4)) : 0;
+    L.W = (d->nx + 63) / 64;
+    const size_t words = (size_t)L.W * d->ny * d->nz;
+    L.bits_off = 0;
+    L.base_off = align_up(words * 8);
+    L.mask_compact = L.base_off + align_up(words * 4);
+    L.mask = std::max(align_up((size_t)N), L.mask_compact);
+    L.max_parts = N / 32 + 64;
+    L.part = 0;
+    L.hist = align_up((size_t)L.max_parts * MP_COUNT * sizeof(double));
+    L.rec = L.hist + align_up(kHistory * sizeof(MonitorRecord));
+    L.stage = L.rec + align_up(sizeof(MonitorRecord));
+    size_t stage = std::min(kStageMax, align_up((size_t)N * (Q + 1) * 8));
+    stage = std::max(stage, align_up((size_t)(Q + 1) * 8 * 256));
+    L.work = L.stage + stage;
+    return L;
+}
+
+}  // namespace
+
+struct lbm_domain {
+    lbm_desc d;
+    lbm_rheology r;
+    int Q = 0, D = 0;
+    int64_t N = 0;
+    Layout L{};
+    bool bound = false;
+    char* pdf = nullptr;
+    void* tau = nullptr;
+    uint8_t* mask = nullptr;
+    char* work = nullptr;
+    hipStream_t stream = nullptr;
+    int cur = 0;     // A/B: copy holding the current post-collision state
+    int parity = 0;  // AA: 0 = post-collision swapped, 1 = streamed natural
+    int64_t t = 0;
+    int tx = 64, ty = 4, tz = 1;
+    int mon_k = 0;
+    int64_t hist_written = 0, hist_read = 0;
+    double umax_limit = 0.1;
+    int64_t S = 0;   // direction stride of the population arrays
+    int64_t Nf = 0;  // fluid nodes
+};
+
+namespace {
+
+int ntiles_of(const lbm_domain* dm, int tx, int ty, int tz)
+{
+    const int64_t nt = (int64_t)((dm->d.nx + tx - 1) / tx) * ((dm->d.ny + ty - 1) / ty) * ((dm->d.nz + tz - 1) / tz);
+    return nt > INT32_MAX ? INT32_MAX : (int)nt;
+}
+
+int check_tile(const lbm_domain* dm, int tx, int ty, int tz)
+{
+    const int th = tx * ty * tz;
+    if (tx < 1 || ty < 1 || tz < 1 || (th != 64 && th != 128 && th != 192 && th != 256))
+        return fail(LBM_EINVAL, "tile %dx%dx%d: threads must be 64, 128, 192 or 256", tx, ty, tz);
+    if (dm->D == 2 && tz != 1) return fail(LBM_EINVAL, "tz must be 1 for D2Q9");
+    if (dm->d.layout == LBM_COMPACT && tx != 64) return fail(LBM_EINVAL, "the compact layout needs tx == 64");
+    if (ntiles_of(dm, tx, ty, tz) > dm->L.max_parts)
+        return fail(LBM_EINVAL, "tile %dx%dx%d leaves too many mostly empty tiles for this domain", tx, ty, tz);
+    return LBM_OK;
+}
+
+int pow2ceil(int v)
+{
+    int p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+void default_tile(lbm_domain* dm)
+{
+    if (dm->d.layout == LBM_COMPACT) {
+        dm->tx = 64;
+        dm->ty = std::min(pow2ceil(dm->d.ny), 4);
+        dm->tz = dm->D == 3 ? std::min(pow2ceil(dm->d.nz), 4 / dm->ty) : 1;
+        return;
+    }
+    int tx = std::min(pow2ceil(dm->d.nx), 64);
+    int ty = std::min(pow2ceil(dm->d.ny), 256 / tx);
+    int tz = dm->D == 3 ? std::min(pow2ceil(dm->d.nz), 256 / (tx * ty)) : 1;
+    while (tx * ty * tz < 64) {
+        if (tx < 64) tx *= 2;
+        else ty *= 2;
+    }
+    dm->tx = tx;
+    dm->ty = ty;
+    dm->tz = tz;
+}
+
+template <class C>
+Coll<C> make_coll(const lbm_rheology& r)
+{
+    Coll<C> c{};
+    c.rho0 = (C)r.rho0;
+    c.nu_p = (C)r.nu_p;
+    c.sigma_y = (C)r.sigma_y;
+    c.m = (C)r.m;
+    c.gamma_c = (C)(r.gamma_c > 0 ? r.gamma_c : 1e-8);
+    c.lambda = (C)r.lambda_trt;
+    for (int a = 0; a < 3; ++a) c.g[a] = (C)r.g[a];
+    c.sqrt2_sy = (C)(std::sqrt(2.0) * r.sigma_y);
+    c.ir_a = (C)((6.0 * r.nu_p - 1.0) / (1.0 + 6.0 * r.nu_p));
+    c.ir_b = (C)(2.0 * std::sqrt(2.0) * r.sigma_y / (1.0 + 6.0 * r.nu_p));
+    const double gc = r.gamma_c > 0 ? r.gamma_c : 1e-8;
+    c.pr_ec = (C)(-std::expm1(-r.m * gc) / gc);
+    c.band = (C)r.fallback_band;
+    return c;
+}
+
+char* copy_ptr(lbm_domain* dm, int k) { return dm->pdf + (size_t)k * dm->L.pdf_copy; }
+
+// Layout code of the stored state (see aux.hip).
+int state_layout(const lbm_domain* dm)
+{
+    if (dm->d.scheme == LBM_AB) return 0;
+    return dm->parity == 0 ? 1 : 2;
+}
+
+NodeArgs node_args(lbm_domain* dm)
+{
+    NodeArgs a{};
+    a.pdf = dm->d.scheme == LBM_AB ? copy_ptr(dm, dm->cur) : dm->pdf;
+    a.tau = dm->tau;
+    a.mask = dm->mask;
+    a.partials = (double*)dm->work;
+    a.N = dm->N;
+    a.nx = dm->d.nx;
+    a.ny = dm->d.ny;
+    a.nz = dm->d.nz;
+    for (int k = 0; k < 3; ++k) a.per[k] = dm->d.periodic[k] ? 1 : 0;
+    if (dm->D == 2) a.per[2] = 1;
+    a.layout = state_layout(dm);
+    a.compact = dm->d.layout == LBM_COMPACT ? 1 : 0;
+    a.bits = (const uint64_t*)(dm->mask + dm->L.bits_off);
+    a.wbase = (const uint32_t*)(dm->mask + dm->L.base_off);
+    a.W = dm->L.W;
+    a.S = dm->S;
+    a.h16_scale = std::ldexp(1.0f, -dm->r.fp16_scale_log2);
+    a.h16_inv = std::ldexp(1.0f, dm->r.fp16_scale_log2);
+    a.cd = make_coll<double>(dm->r);
+    a.cf = make_coll<float>(dm->r);
+    return a;
+}
+
+StepArgs step_args(lbm_domain* dm)
+{
+    StepArgs a{};
+    a.tau = dm->tau;
+    a.mask = dm->mask;
+    a.bits = (const uint64_t*)(dm->mask + dm->L.bits_off);
+    a.wbase = (const uint32_t*)(dm->mask + dm->L.base_off);
+    a.W = dm->L.W;
+    a.S = dm->S;
+    a.partials = (double*)dm->work;
+    a.N = dm->N;
+    a.nx = dm->d.nx;
+    a.ny = dm->d.ny;
+    a.nz = dm->d.nz;
+    for (int k = 0; k < 3; ++k) a.per[k] = dm->d.periodic[k] ? 1 : 0;
+    if (dm->D == 2) a.per[2] = 1;
+    a.tx = dm->tx;
+    a.ty = dm->ty;
+    a.tz = dm->tz;
+    a.ntx = (dm->d.nx + dm->tx - 1) / dm->tx;
+    a.nty = (dm->d.ny + dm->ty - 1) / dm->ty;
+    a.ntz = (dm->d.nz + dm->tz - 1) / dm->tz;
+    a.ntiles = a.ntx * a.nty * a.ntz;
+    a.tiles_per_xcd = (a.ntiles + 7) / 8;
+    a.fallback = (dm->d.precision != LBM_FP64 && dm->r.fp64_fallback) ? 1 : 0;
+    a.h16_scale = std::ldexp(1.0f, -dm->r.fp16_scale_log2);
+    a.h16_inv = std::ldexp(1.0f, dm->r.fp16_scale_log2);
+    a.cd = make_coll<double>(dm->r);
+    a.cf = make_coll<float>(dm->r);
+    return a;
+}
+
+int need_bound(lbm_domain* dm)
+{
+    if (!dm) return fail(LBM_EINVAL, "domain is NULL");
+    if (!dm->bound) return fail(LBM_ESTATE, "domain has no bound buffers (call lbm_bind)");
+    return LBM_OK;
+}
+
+int64_t chunk_nodes(const lbm_domain* dm, size_t bytes_per_node)
+{
+    const size_t stage = dm->L.work - dm->L.stage;
+    return std::max<int64_t>(1, std::min<int64_t>(dm->N, (int64_t)(stage / bytes_per_node)));
+}
+
+int run_steps(lbm_domain* dm, int64_t nsteps)
+{
+    StepArgs a = step_args(dm);
+    if (a.ntiles > dm->L.max_parts)
+        return fail(LBM_EINVAL, "tile %dx%dx%d gives %d tiles, more than the %lld monitor slots", dm->tx, dm->ty,
+                    dm->tz, a.ntiles, (long long)dm->L.max_parts);
+    // the population stride must cover every slot the layout addresses
+    if ((dm->d.layout == LBM_DENSE && dm->S != dm->N) || (dm->d.layout == LBM_COMPACT && dm->S < dm->Nf) ||
+        dm->S > dm->L.npad || (dm->d.layout == LBM_COMPACT && dm->tx != 64))
+        return fail(LBM_ESTATE, "inconsistent population stride or tile for the layout");
+    for (int64_t s = 0; s < nsteps; ++s) {
+        int pat;
+        if (dm->d.scheme == LBM_AB) {
+            pat = PAT_AB;
+            a.src = copy_ptr(dm, dm->cur);
+            a.dst = copy_ptr(dm, 1 - dm->cur);
+        } else {
+            pat = dm->parity == 0 ? PAT_AA_PULL : PAT_AA_LOCAL;
+            a.src = dm->pdf;
+            a.dst = dm->pdf;
+        }
+        const bool mon = dm->mon_k > 0 && (dm->t % dm->mon_k) == 0;
+        HIPCHK(launch_step(dm->d.lattice, dm->r.op, dm->d.precision, pat, mon, dm->d.layout, a, dm->stream));
+        if (mon) {
+            char* rec = dm->work + dm->L.hist + (size_t)(dm->hist_written % kHistory) * sizeof(MonitorRecord);
+            HIPCHK(launch_finalize((double*)dm->work, a.ntiles, rec, dm->t, (double)dm->N, dm->stream));
+            dm->hist_written++;
+        }
+        if (dm->d.scheme == LBM_AB) dm->cur = 1 - dm->cur;
+        else dm->parity ^= 1;
+        dm->t++;
+    }
+    return LBM_OK;
+}
+
+// Upload a host mask (nullptr = all fluid) in the domain's layout and set
+// the population stride.
+int upload_mask(lbm_domain* dm, const uint8_t* host_mask)
+{
+    if (dm->d.layout == LBM_DENSE) {
+        if (host_mask) {
+            HIPCHK(hipMemcpyAsync(dm->mask, host_mask, (size_t)dm->N, hipMemcpyHostToDevice, dm->stream));
+            int64_t nf = 0;
+            for (int64_t n = 0; n < dm->N; ++n) nf += host_mask[n] == 0;
+            dm->Nf = nf;
+        } else {
+            HIPCHK(launch_fill_u8(dm->mask, dm->N, 0, dm->stream));
+            dm->Nf = dm->N;
+        }
+        dm->S = dm->N;
+        HIPCHK(hipStreamSynchronize(dm->stream));
+        return LBM_OK;
+    }
+    const int nx = dm->d.nx, W = dm->L.W;
+    const int64_t rows = (int64_t)dm->d.ny * dm->d.nz;
+    std::vector<uint64_t> bits((size_t)rows * W, 0);
+    std::vector<uint32_t> base((size_t)rows * W, 0);
+    uint64_t count = 0;
+    for (int64_t r = 0; r < rows; ++r) {
+        for (int w = 0; w < W; ++w) {
+            uint64_t word = 0;
+            for (int b = 0; b < 64; ++b) {
+                const int x = 64 * w + b;
+                if (x < nx && (!host_mask || host_mask[r * nx + x] == 0)) word |= 1ull << b;
+            }
+            bits[(size_t)r * W + w] = word;
+            base[(size_t)r * W + w] = (uint32_t)count;
+            count += (uint64_t)__builtin_popcountll(word);
+            if (count > 0xFFFFFFFFull) return fail(LBM_EINVAL, "compact layout holds at most 2^32-1 fluid nodes");
+        }
+    }
+    dm->Nf = (int64_t)count;
+    dm->S = std::max<int64_t>(64, (dm->Nf + 63) / 64 * 64);
+    HIPCHK(hipMemcpyAsync(dm->mask + dm->L.bits_off, bits.data(), bits.size() * 8, hipMemcpyHostToDevice, dm->stream));
+    HIPCHK(hipMemcpyAsync(dm->mask + dm->L.base_off, base.data(), base.size() * 4, hipMemcpyHostToDevice, dm->stream));
+    HIPCHK(hipStreamSynchronize(dm->stream));
+    return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lbm_last_error(void) { return g_err.c_str(); }
+
+int lbm_lattice_info(int32_t lattice, int32_t* q, int32_t* c, double* w, int32_t* opp)
+{
+    auto fill = [&](auto L) {
+        using LT = decltype(L);
+        if (q) *q = LT::Q;
+        for (int i = 0; i < LT::Q; ++i) {
+            if (c) { c[3 * i] = LT::cx[i]; c[3 * i + 1] = LT::cy[i]; c[3 * i + 2] = LT::cz[i]; }
+            if (w) w[i] = LT::w[i];
+            if (opp) opp[i] = lbm::opp(i);
+        }
+        return LBM_OK;
+    };
+    switch (lattice) {
+    case 0: return fill(Lattice<0>{});
+    case 1: return fill(Lattice<1>{});
+    case 2: return fill(Lattice<2>{});
+    default: return fail(LBM_EINVAL, "unknown lattice %d", lattice);
+    }
+}
+
+int lbm_query_sizes(const lbm_desc* desc, const lbm_rheology* rh, lbm_sizes* out)
+{
+    int rc = check_desc(desc);
+    if (rc) return rc;
+    if (rh && (rc = check_rheology(rh))) return rc;
+    if (!out) return fail(LBM_EINVAL, "out is NULL");
+    const Layout L = layout_of(desc, rh);
+    out->pdf_bytes = L.pdf;
+    out->tau_bytes = L.tau;
+    out->mask_bytes = L.mask;
+    out->work_bytes = L.work;
+    return LBM_OK;
+}
+
+int lbm_create(const lbm_desc* desc, const lbm_rheology* rh, lbm_domain** out)
+{
+    int rc = check_desc(desc);
+    if (rc) return rc;
+    if ((rc = check_rheology(rh))) return rc;
+    if (!out) return fail(LBM_EINVAL, "out is NULL");
+    lbm_domain* dm = new (std::nothrow) lbm_domain();
+    if (!dm) return fail(LBM_EINVAL, "host allocation failed");
+    dm->d = *desc;
+    dm->r = *rh;
+    dm->Q = lattice_q(desc->lattice);
+    dm->D = lattice_d(desc->lattice);
+    dm->N = (int64_t)desc->nx * desc->ny * desc->nz;
+    dm->L = layout_of(desc, rh);
+    default_tile(dm);
+    *out = dm;
+    return LBM_OK;
+}
+
+int lbm_bind(lbm_domain* dm, void* pdf_dev, void* tau_dev, void* mask_dev, void* work_dev, void* hip_stream)
+{
+    if (!dm) return fail(LBM_EINVAL, "domain is NULL");
+    if (!pdf_dev || !mask_dev || !work_dev) return fail(LBM_EINVAL, "pdf, mask and work buffers are required");
+    if (dm->r.op == LBM_PR && !tau_dev) return fail(LBM_EINVAL, "the PR operator needs the tau buffer");
+    if (((uintptr_t)pdf_dev | (uintptr_t)work_dev | (uintptr_t)(tau_dev ? tau_dev : pdf_dev)) % 16)
+        return fail(LBM_EINVAL, "device buffers must be 16-byte aligned");
+    dm->pdf = (char*)pdf_dev;
+    dm->tau = tau_dev;
+    dm->mask = (uint8_t*)mask_dev;
+    dm->work = (char*)work_dev;
+    dm->stream = (hipStream_t)hip_stream;
+    dm->bound = true;
+    int rc = upload_mask(dm, nullptr);
+    if (rc) return rc;
+    const double zero[3] = {0, 0, 0};
+    return lbm_init_equilibrium(dm, dm->r.rho0, zero);
+}
+
+int lbm_set_mask(lbm_domain* dm, const uint8_t* host_mask)
+{
+    int rc = need_bound(dm);
+    if (rc) return rc;
+    if (!host_mask) return fail(LBM_EINVAL, "host_mask is NULL");
+    if ((rc = upload_mask(dm, host_mask))) return rc;
+    const double zero[3] = {0, 0, 0};
+    return lbm_init_equilibrium(dm, dm->r.rho0, zero);
+}
+
+int lbm_init_equilibrium(lbm_domain* dm, double rho0, const double* u0)
+{
+    int rc = need_bound(dm);
+    if (rc) return rc;
+    if (!(rho0 > 0)) return fail(LBM_EINVAL, "rho0 must be > 0");
+    dm->cur = 0;
+    dm->parity = 0;
+    dm->t = 0;
+    dm->hist_written = dm->hist_read = 0;
+    NodeArgs a = node_args(dm);
+    for (int k = 0; k < 3; ++k) a.u0[k] = u0 ? u0[k] : 0.0;
+    HIPCHK(launch_init(dm->d.lattice, dm->r.op, dm->d.precision, a, rho0, dm->stream));
+    return LBM_OK;
+}
+
+int lbm_write_populations(lbm_domain* dm, const double* host_P, const double* host_tau)
+{
+    int rc = need_bound(dm);
+    if (rc) return rc;
+    if (!host_P) return fail(LBM_EINVAL, "host_P is NULL");
+    if (dm->d.scheme == LBM_AA) dm->parity = 0;  // written as post-collision, swapped
+    const int Q = dm->Q;
+    const int64_t chunk = chunk_nodes(dm, (size_t)(Q + 1) * 8);
+    double* stage = (double*)(dm->work + dm->L.stage);
+    for (int64_t n0 = 0; n0 < dm->N; n0 += chunk) {
+        const int64_t cnt = std::min(chunk, dm->N - n0);
+        HIPCHK(hipMemcpy2DAsync(stage, cnt * 8, host_P + n0, dm->N * 8, cnt * 8, Q, hipMemcpyHostToDevice, dm->stream));
+        NodeArgs a = node_args(dm);
+        a.tau = nullptr;
+        if (host_tau && dm->tau) {
+            HIPCHK(hipMemcpyAsync(stage + (size_t)Q * cnt, host_tau + n0, cnt * 8, hipMemcpyHostToDevice, dm->stream));
+            a.tau = dm->tau;
+        }
+        a.out = stage;
+        a.n0 = n0;
+        a.count = cnt;
+        HIPCHK(launch_pop_write(dm->d.lattice, dm->d.precision, a, dm->stream));
+        HIPCHK(hipStreamSynchronize(dm->stream));
+    }
+    return LBM_OK;
+}
+
+int lbm_read_populations(lbm_domain* dm, double* host_P, double* host_tau)
+{
+    int rc = need_bound(dm);
+    if (rc) return rc;
+    if (!host_P) return fail(LBM_EINVAL, "host_P is NULL");
+    const int Q = dm->Q;
+    const int64_t chunk = chunk_nodes(dm, (size_t)(Q + 1) * 8);
+    double* stage = (double*)(dm->work + dm->L.stage);
+    for (int64_t n0 = 0; n0 < dm->N; n0 += chunk) {
+        const int64_t cnt = std::min(chunk, dm->N - n0);
+        NodeArgs a = node_args(dm);
+        if (!(host_tau && dm->tau)) a.tau = nullptr;
+        a.out = stage;
+        a.n0 = n0;
+        a.count = cnt;
+        HIPCHK(launch_pop_read(dm->d.lattice, dm->d.precision, a, dm->stream));
+        HIPCHK(hipMemcpy2DAsync(host_P + n0, dm->N * 8, stage, cnt * 8, cnt * 8, Q, hipMemcpyDeviceToHost, dm->stream));
+        if (a.tau)
+            HIPCHK(hipMemcpyAsync(host_tau + n0, stage + (size_t)Q * cnt, cnt * 8, hipMemcpyDeviceToHost, dm->stream));
+        HIPCHK(hipStreamSynchronize(dm->stream));
+    }
+    return LBM_OK;
+}
+
+int lbm_step(lbm_domain* dm, int64_t nsteps)
+{
+    int rc = need_bound(dm);
+    if (rc) return rc;
+    if (nsteps < 0) return fail(LBM_EINVAL, "nsteps must be >= 0");
+    return run_steps(dm, nsteps);
+}
+
+int lbm_time(lbm_domain* dm, int64_t* t)
+{
+    if (!dm || !t) return fail(LBM_EINVAL, "NULL argument");
+    *t = dm->t;
+    return LBM_OK;
+}
+
+int lbm_set_monitor_interval(lbm_domain* dm, int32_t k)
+{
+    if (!dm) return fail(LBM_EINVAL, "domain is NULL");
+    if (k < 0) return fail(LBM_EINVAL, "interval must be >= 0");
+    dm->mon_k = k;
+    return LBM_OK;
+}
+
+int lbm_read_history(lbm_domain* dm, lbm_monitor* out, int32_t max, int32_t* count)
+{
+    int rc = need_bound(dm);
+    if (rc) return rc;
+    if (!count || (max > 0 && !out)) return fail(LBM_EINVAL, "NULL argument");
+    HIPCHK(hipStreamSynchronize(dm->stream));
+    dm->hist_read = std::max(dm->hist_read, dm->hist_written - kHistory);
+    const int64_t n = std::min<int64_t>(dm->hist_written - dm->hist_read, max);
+    const MonitorRecord* ring = (const MonitorRecord*)(dm->work + dm->L.hist);
+    for (int64_t k = 0; k < n; ++k) {
+        const int64_t slot = (dm->hist_read + k) % kHistory;
+        HIPCHK(hipMemcpy(out + k, ring + slot, sizeof(MonitorRecord), hipMemcpyDeviceToHost));
+    }
+    dm->hist_read += n;
+    *count = (int32_t)n;
+    return LBM_OK;
+}
+
+int lbm_monitors(lbm_domain* dm, lbm_monitor* out)
+{
+    int rc = need_bound(dm);
+    if (rc) return rc;
+    if (!out) return fail(LBM_EINVAL, "out is NULL");
+    NodeArgs a = node_args(dm);
+    a.n0 = 0;
+    a.count = dm->N;
+    a.reduce = 1;
+    int64_t nb = 0;
+    HIPCHK(launch_readout(dm->d.lattice, dm->r.op, dm->d.precision, a, dm->stream, &nb));
+    char* rec = dm->work + dm->L.rec;
+    HIPCHK(launch_finalize((double*)dm->work, nb, rec, dm->t, (double)dm->N, dm->stream));
+    HIPCHK(hipMemcpyAsync(out, rec, sizeof(MonitorRecord), hipMemcpyDeviceToHost, dm->stream));
+    HIPCHK(hipStreamSynchronize(dm->stream));
+    if (out->nonfinite > 0) return fail(LBM_EUNSTABLE, "%lld non-finite fluid nodes at step %lld",
+                                        (long long)out->nonfinite, (long long)out->step);
+    if (out->umax > dm->umax_limit)
+        return fail(LBM_EUNSTABLE, "max |u| = %g exceeds %g at step %lld", out->umax, dm->umax_limit,
+                    (long long)out->step);
+    return LBM_OK;
+}
+
+int lbm_set_umax_limit(lbm_domain* dm, double umax)
+{
+    if (!dm) return fail(LBM_EINVAL, "domain is NULL");
+    if (!(umax > 0)) return fail(LBM_EINVAL, "umax limit must be > 0");
+    dm->umax_limit = umax;
+    return LBM_OK;
+}
+
+int lbm_read_moments(lbm_domain* dm, double* rho, double* u, double* nu_app, uint8_t* unyielded)
+{
+    int rc = need_bound(dm);
+    if (rc) return rc;
+    const int64_t chunk = chunk_nodes(dm, 5 * 8 + 1);
+    double* stage = (double*)(dm->work + dm->L.stage);
+    for (int64_t n0 = 0; n0 < dm->N; n0 += chunk) {
+        const int64_t cnt = std::min(chunk, dm->N - n0);
+        NodeArgs a = node_args(dm);
+        a.out = stage;
+        a.out_flags = (uint8_t*)(stage + 5 * cnt);
+        a.n0 = n0;
+        a.count = cnt;
+        HIPCHK(launch_readout(dm->d.lattice, dm->r.op, dm->d.precision, a, dm->stream, nullptr));
+        if (rho) HIPCHK(hipMemcpyAsync(rho + n0, stage, cnt * 8, hipMemcpyDeviceToHost, dm->stream));
+        if (u)
+            for (int k = 0; k < 3; ++k)
+                HIPCHK(hipMemcpyAsync(u + (size_t)k * dm->N + n0, stage + (size_t)(1 + k) * cnt, cnt * 8,
+                                      hipMemcpyDeviceToHost, dm->stream));
+        if (nu_app) HIPCHK(hipMemcpyAsync(nu_app + n0, stage + 4 * cnt, cnt * 8, hipMemcpyDeviceToHost, dm->stream));
+        if (unyielded)
+            HIPCHK(hipMemcpyAsync(unyielded + n0, a.out_flags, cnt, hipMemcpyDeviceToHost, dm->stream));
+        HIPCHK(hipStreamSynchronize(dm->stream));
+    }
+    return LBM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// checkpoints
+// ---------------------------------------------------------------------------
+namespace {
+struct CkptHeader {
+    char magic[8];
+    uint32_t version, header_bytes;
+    lbm_desc desc;
+    lbm_rheology rh;
+    int64_t t, stride, fluid;
+    int32_t parity, q;
+    uint64_t pdf_bytes, tau_bytes, mask_bytes;
+};
+const char kMagic[8] = {'L', 'B', 'M', 'C', 'K', 'P', 'T', '1'};
+}  // namespace
+
+int lbm_save(lbm_domain* dm, void* blob, size_t* bytes)
+{
+    int rc = need_bound(dm);
+    if (rc) return rc;
+    if (!bytes) return fail(LBM_EINVAL, "bytes is NULL");
+    CkptHeader h{};
+    memcpy(h.magic, kMagic, 8);
+    h.version = 1;
+    h.header_bytes = sizeof(CkptHeader);
+    h.desc = dm->d;
+    h.rh = dm->r;
+    h.t = dm->t;
+    h.stride = dm->S;
+    h.fluid = dm->Nf;
+    h.parity = dm->parity;
+    h.q = dm->Q;
+    h.pdf_bytes = (uint64_t)dm->Q * dm->S * prec_bytes(dm->d.precision);
+    h.tau_bytes = dm->tau ? (uint64_t)dm->S * (dm->d.precision == LBM_FP64 ? 8 : 4) : 0;
+    h.mask_bytes = dm->d.layout == LBM_DENSE ? (uint64_t)dm->N : (uint64_t)dm->L.mask_compact;
+    const size_t need = sizeof(h) + h.pdf_bytes + h.tau_bytes + h.mask_bytes;
+    if (!blob) {
+        *bytes = need;
+        return LBM_OK;
+    }
+    if (*bytes < need) return fail(LBM_EINVAL, "blob too small: %zu < %zu", *bytes, need);
+    char* p = (char*)blob;
+    HIPCHK(hipStreamSynchronize(dm->stream));
+    memcpy(p, &h, sizeof h);
+    p += sizeof h;
+    const char* src = dm->d.scheme == LBM_AB ? copy_ptr(dm, dm->cur) : dm->pdf;
+    HIPCHK(hipMemcpy(p, src, h.pdf_bytes, hipMemcpyDeviceToHost));
+    p += h.pdf_bytes;
+    if (h.tau_bytes) HIPCHK(hipMemcpy(p, dm->tau, h.tau_bytes, hipMemcpyDeviceToHost));
+    p += h.tau_bytes;
+    HIPCHK(hipMemcpy(p, dm->mask, h.mask_bytes, hipMemcpyDeviceToHost));
+    *bytes = need;
+    return LBM_OK;
+}
+
+int lbm_load(lbm_domain* dm, const void* blob, size_t bytes)
+{
+    int rc = need_bound(dm);
+    if (rc) return rc;
+    if (!blob) return fail(LBM_EINVAL, "blob is NULL");
+    CkptHeader h;
+    if (bytes < sizeof h) return fail(LBM_EFORMAT, "checkpoint truncated (header)");
+    memcpy(&h, blob, sizeof h);
+    if (memcmp(h.magic, kMagic, 8) != 0 || h.version != 1 || h.header_bytes != sizeof h)
+        return fail(LBM_EFORMAT, "not a checkpoint of this library version");
+    if (memcmp(&h.desc, &dm->d, sizeof(lbm_desc)) != 0 || h.q != dm->Q)
+        return fail(LBM_EFORMAT, "checkpoint was saved from a different domain descriptor");
+    const uint64_t mask_expect = dm->d.layout == LBM_DENSE ? (uint64_t)dm->N : (uint64_t)dm->L.mask_compact;
+    if (h.stride < 1 || h.stride > dm->L.npad || h.fluid < 0 || h.fluid > h.stride)
+        return fail(LBM_EFORMAT, "checkpoint stride does not fit the domain");
+    const uint64_t tau_expect = dm->tau ? (uint64_t)h.stride * (dm->d.precision == LBM_FP64 ? 8 : 4) : 0;
+    if (h.pdf_bytes != (uint64_t)dm->Q * h.stride * prec_bytes(dm->d.precision) || h.tau_bytes != tau_expect ||
+        h.mask_bytes != mask_expect)
+        return fail(LBM_EFORMAT, "checkpoint sizes do not match the domain");
+    if (bytes < sizeof h + h.pdf_bytes + h.tau_bytes + h.mask_bytes) return fail(LBM_EFORMAT, "checkpoint truncated");
+    const char* p = (const char*)blob + sizeof h;
+    HIPCHK(hipStreamSynchronize(dm->stream));
+    dm->cur = 0;
+    HIPCHK(hipMemcpy(dm->pdf, p, h.pdf_bytes, hipMemcpyHostToDevice));
+    p += h.pdf_bytes;
+    if (h.tau_bytes) HIPCHK(hipMemcpy(dm->tau, p, h.tau_bytes, hipMemcpyHostToDevice));
+    p += h.tau_bytes;
+    HIPCHK(hipMemcpy(dm->mask, p, h.mask_bytes, hipMemcpyHostToDevice));
+    dm->t = h.t;
+    dm->S = h.stride;
+    dm->Nf = h.fluid;
+    dm->parity = h.parity;
+    dm->hist_written = dm->hist_read = 0;
+    return LBM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// tiles
+// ---------------------------------------------------------------------------
+int lbm_set_tile(lbm_domain* dm, int32_t tx, int32_t ty, int32_t tz)
+{
+    if (!dm) return fail(LBM_EINVAL, "domain is NULL");
+    int rc = check_tile(dm, tx, ty, tz);
+    if (rc) return rc;
+    dm->tx = tx;
+    dm->ty = ty;
+    dm->tz = tz;
+    return LBM_OK;
+}
+
+int lbm_get_tile(lbm_domain* dm, int32_t* tx, int32_t* ty, int32_t* tz)
+{
+    if (!dm || !tx || !ty || !tz) return fail(LBM_EINVAL, "NULL argument");
+    *tx = dm->tx;
+    *ty = dm->ty;
+    *tz = dm->tz;
+    return LBM_OK;
+}
+
+int lbm_autotune(lbm_domain* dm, int32_t trial_steps)
+{
+    int rc = need_bound(dm);
+    if (rc) return rc;
+    if (trial_steps < 1) return fail(LBM_EINVAL, "trial_steps must be >= 1");
+    // candidate shapes: wavefront-wide rows first, then squatter tiles
+    static const int cand3[][3] = {{256, 1, 1}, {128, 2, 1}, {64, 4, 1}, {64, 2, 2}, {128, 1, 2},
+                                   {32, 8, 1},  {32, 4, 2}, {64, 1, 4}, {16, 4, 4}, {64, 2, 1},
+                                   {64, 1, 1},  {128, 1, 1}};
+    static const int cand2[][3] = {{256, 1, 1}, {128, 2, 1}, {64, 4, 1}, {32, 8, 1}, {16, 16, 1},
+                                   {8, 32, 1},  {4, 64, 1},  {64, 2, 1}, {64, 1, 1}, {128, 1, 1}};
+    // save the state; trial steps run on it and it is restored afterwards
+    size_t bytes = 0;
+    if ((rc = lbm_save(dm, nullptr, &bytes))) return rc;
+    std::vector<char> saved(bytes);
+    if ((rc = lbm_save(dm, saved.data(), &bytes))) return rc;
+    const int mon_k = dm->mon_k;
+    dm->mon_k = 0;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    static const int candc3[][3] = {{64, 4, 1}, {64, 2, 2}, {64, 1, 4}, {64, 2, 1}, {64, 1, 2}, {64, 1, 1}};
+    static const int candc2[][3] = {{64, 4, 1}, {64, 2, 1}, {64, 1, 1}};
+    const int (*cand)[3];
+    int nc;
+    if (dm->d.layout == LBM_COMPACT) {
+        cand = dm->D == 3 ? candc3 : candc2;
+        nc = dm->D == 3 ? 6 : 3;
+    } else {
+        cand = dm->D == 3 ? cand3 : cand2;
+        nc = dm->D == 3 ? (int)(sizeof cand3 / sizeof cand3[0]) : (int)(sizeof cand2 / sizeof cand2[0]);
+    }
+    int best = -1;
+    float best_ms = 1e30f;
+    const int keep[3] = {dm->tx, dm->ty, dm->tz};
+    for (int c = 0; c < nc; ++c) {
+        const int tx = cand[c][0], ty = cand[c][1], tz = cand[c][2];
+        if (check_tile(dm, tx, ty, tz) != LBM_OK) continue;
+        if (tx > 2 * pow2ceil(dm->d.nx) || ty > 2 * pow2ceil(dm->d.ny)) continue;
+        dm->tx = tx;
+        dm->ty = ty;
+        dm->tz = tz;
+        if ((rc = run_steps(dm, 2))) break;
+        HIPCHK(hipEventRecord(e0, dm->stream));
+        if ((rc = run_steps(dm, trial_steps))) break;
+        HIPCHK(hipEventRecord(e1, dm->stream));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    dm->mon_k = mon_k;
+    if (best >= 0) {
+        dm->tx = cand[best][0];
+        dm->ty = cand[best][1];
+        dm->tz = cand[best][2];
+    } else {
+        dm->tx = keep[0];
+        dm->ty = keep[1];
+        dm->tz = keep[2];
+    }
+    const int rc_load = lbm_load(dm, saved.data(), bytes);
+    if (rc) return rc;
+    return rc_load;
+}
+
+int lbm_destroy(lbm_domain* dm)
+{
+    if (!dm) return LBM_OK;
+    if (dm->bound && dm->stream) (void)hipStreamSynchronize(dm->stream);
+    delete dm;
+    return LBM_OK;
+}
+
+}  // extern "C"

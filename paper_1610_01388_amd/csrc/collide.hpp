@@ -1,0 +1,252 @@
+// collide.hpp -- node-local physics of the GPU library: moments, the
+// Papanastasiou-regularised (PR) and implicitly-regularised (IR) collision of
+// Regulski, Leonardi & Szumbarski (arXiv:1610.01388).
+//
+// All functions work on deviations h_i = f_i - w_i rho0 of the transformed
+// populations (Sec. 2, Eq. 11), which keeps the small non-equilibrium
+// moments accurate in reduced precision.  With Pi' = sum c c h the moments
+// are rho = rho0 + sum h, j = sum c h, Pi = Pi' + rho0 cs^2 I.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "lattice.hpp"
+
+namespace lbm {
+
+enum { OP_PR = 0, OP_IR = 1 };
+
+__device__ __forceinline__ double d_sqrt(double v) { return sqrt(v); }
+__device__ __forceinline__ float d_sqrt(float v) { return sqrtf(v); }
+__device__ __forceinline__ double d_expm1(double v) { return expm1(v); }
+__device__ __forceinline__ float d_expm1(float v) { return expm1f(v); }
+
+// Per-launch constants in compute precision C.
+template <class C> struct Coll {
+    C rho0, nu_p, sigma_y, m, gamma_c, lambda, g[3];
+    C sqrt2_sy;   // sqrt(2) sigma_y: IR yield threshold on |dev T|
+    C ir_a, ir_b; // IR yielded: lambda = ir_a + ir_b / T, ir_a = (6nu_p-1)/(1+6nu_p),
+                  // ir_b = 2 sqrt2 sigma_y/(1+6nu_p)  (Eqs. 39-40 combined)
+    C pr_ec;      // PR: -expm1(-m gamma_c) / gamma_c  (nu_app at the cut-off is nu_p + sigma_y pr_ec / rho)
+    C band;       // FP64 fallback band
+};
+
+template <class C> struct Moments {
+    C drho, j[3];
+    C p[6];  // Pi' = sum c c h: xx, yy, zz, xy, xz, yz
+};
+
+// Node state after the rheology solve, before relaxation.
+template <class C> struct Pre {
+    C rho, u[3];  // u: velocity inside the equilibrium (PR: j/rho; IR: j/rho + g/2)
+    C a[6];       // IR: post-collision stress tensor A = lambda dev(T)
+    C tau_p, tau_m, nu_app, gamma, Tn;
+    bool unyielded, near_yield;
+};
+
+template <int LAT, class C>
+__device__ __forceinline__ void add_c(C& acc, C v, int c)
+{
+    if (c == 1) acc += v;
+    else if (c == -1) acc -= v;
+}
+
+// Eq. 9: zeroth, first and second moments (of the deviations).
+template <int LAT, class C>
+__device__ __forceinline__ Moments<C> moments(const C (&h)[Lattice<LAT>::Q])
+{
+    using L = Lattice<LAT>;
+    Moments<C> mo;
+    mo.drho = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) mo.j[a] = 0;
+#pragma unroll
+    for (int a = 0; a < 6; ++a) mo.p[a] = 0;
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        const C v = h[i];
+        mo.drho += v;
+        add_c<LAT>(mo.j[0], v, L::cx[i]);
+        add_c<LAT>(mo.j[1], v, L::cy[i]);
+        add_c<LAT>(mo.j[2], v, L::cz[i]);
+        add_c<LAT>(mo.p[0], v, L::cx[i] * L::cx[i]);
+        add_c<LAT>(mo.p[1], v, L::cy[i] * L::cy[i]);
+        add_c<LAT>(mo.p[2], v, L::cz[i] * L::cz[i]);
+        add_c<LAT>(mo.p[3], v, L::cx[i] * L::cy[i]);
+        add_c<LAT>(mo.p[4], v, L::cx[i] * L::cz[i]);
+        add_c<LAT>(mo.p[5], v, L::cy[i] * L::cz[i]);
+    }
+    return mo;
+}
+
+// Non-equilibrium second moment Pi - rho cs^2 I - rho v v, from the
+// deviation moments: Pi' - drho cs^2 I_d - rho v v.
+template <int LAT, class C>
+__device__ __forceinline__ void noneq_second(const Moments<C>& mo, C rho, const C (&v)[3], C (&t)[6])
+{
+    constexpr int D = Lattice<LAT>::D;
+    const C third = C(1) / C(3);
+    t[0] = mo.p[0] - mo.drho * third - rho * v[0] * v[0];
+    t[1] = mo.p[1] - mo.drho * third - rho * v[1] * v[1];
+    t[2] = (D == 3) ? mo.p[2] - mo.drho * third - rho * v[2] * v[2] : C(0);
+    t[3] = mo.p[3] - rho * v[0] * v[1];
+    t[4] = (D == 3) ? mo.p[4] - rho * v[0] * v[2] : C(0);
+    t[5] = (D == 3) ? mo.p[5] - rho * v[1] * v[2] : C(0);
+}
+
+template <class C>
+__device__ __forceinline__ C frob2(const C (&t)[6])
+{
+    return t[0] * t[0] + t[1] * t[1] + t[2] * t[2] + C(2) * (t[3] * t[3] + t[4] * t[4] + t[5] * t[5]);
+}
+
+// Rheology: everything up to, but not including, the relaxation.
+//  PR (Sec. 2.2 Eq. 24, Sec. 3.1 Eqs. 36-37, Sec. 2.1): D from the
+//   non-equilibrium second moment at the bare velocity with the previous
+//   step's tau (density kept, as in Eq. 33), gamma = sqrt(2 D:D) on the full
+//   tensor, nu_app with the linear interpolation below gamma_c (denominator
+//   gamma_c), tau_even = 1/2 + 3 nu_app, tau_odd from Lambda.
+//  IR (Sec. 2.3, 3.2): T = sum c c (f - f_eq + Phi/2) at u = (j + F/2)/rho,
+//   deviatoric part (trace / d), yielded iff |dev T| > sqrt(2) sigma_y,
+//   A = -sigma + s/2 = lambda dev T with the closed forms of Eqs. 39-40.
+template <int LAT, int OP, class C>
+__device__ __forceinline__ Pre<C> rheology(const Moments<C>& mo, const Coll<C>& p, C tau_prev)
+{
+    constexpr int D = Lattice<LAT>::D;
+    Pre<C> r;
+    r.rho = p.rho0 + mo.drho;
+    const C irho = C(1) / r.rho;
+    if (OP == OP_PR) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) r.u[a] = mo.j[a] * irho;
+        C t[6];
+        noneq_second<LAT>(mo, r.rho, r.u, t);
+        const C coef = C(-1.5) / (r.rho * tau_prev);  // -1 / (2 rho cs^2 tau)
+        C dd[6];
+#pragma unroll
+        for (int a = 0; a < 6; ++a) dd[a] = coef * t[a];
+        const C gamma = d_sqrt(C(2) * frob2(dd));
+        C nu;
+        if (gamma >= p.gamma_c) {
+            nu = p.nu_p + p.sigma_y * irho * (-d_expm1(-p.m * gamma)) / gamma;
+        } else {
+            const C nu0 = p.nu_p + p.m * p.sigma_y * irho;
+            const C nuc = p.nu_p + p.sigma_y * irho * p.pr_ec;
+            nu = nu0 + (gamma / p.gamma_c) * (nuc - nu0);
+        }
+        r.nu_app = nu;
+        r.gamma = gamma;
+        r.tau_p = C(0.5) + C(3) * nu;
+        r.tau_m = C(0.5) + p.lambda / (r.tau_p - C(0.5));
+        r.unyielded = r.rho * nu * gamma < p.sigma_y;
+        r.near_yield = p.m * gamma < p.band;
+        r.Tn = 0;
+    } else {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) r.u[a] = mo.j[a] * irho + C(0.5) * p.g[a];
+        C t[6];
+        noneq_second<LAT>(mo, r.rho, r.u, t);
+        const C tr = (D == 3) ? t[0] + t[1] + t[2] : t[0] + t[1];
+        const C trd = tr / C(D);
+        t[0] -= trd;
+        t[1] -= trd;
+        if (D == 3) t[2] -= trd;
+        const C Tn = d_sqrt(frob2(t));
+        const bool yielded = Tn > p.sqrt2_sy;
+        C lam = C(1);
+        if (yielded) lam = p.ir_a + p.ir_b / Tn;
+#pragma unroll
+        for (int a = 0; a < 6; ++a) r.a[a] = lam * t[a];
+        r.Tn = Tn;
+        r.unyielded = !yielded;
+        r.near_yield = p.sigma_y > C(0) && fabs(Tn - p.sqrt2_sy) < p.band * p.sqrt2_sy;
+        r.tau_p = tau_prev;
+        r.tau_m = tau_prev;
+        r.nu_app = p.nu_p;
+        r.gamma = 0;
+    }
+    return r;
+}
+
+// Relaxation: overwrite h with the post-collision deviations.
+//  PR: TRT on the even/odd parts of h - h_eq, plus the EDM difference
+//   f_eq(u + g) - f_eq(u) written out (Sec. 2.4, Eq. 34).
+//  IR: f_eq(u) + f_sigma + Phi/2 with f_sigma = w/(2 cs^4)(c c - cs^2 I):A
+//   and Phi = 3 w c.F, F = rho g (Sec. 2.3 Eqs. 28-29, Sec. 2.4 Eq. 35).
+template <int LAT, int OP, class C>
+__device__ __forceinline__ void relax(C (&h)[Lattice<LAT>::Q], const Moments<C>& mo, const Pre<C>& r,
+                                      const Coll<C>& p)
+{
+    using L = Lattice<LAT>;
+    const C* u = r.u;
+    const C uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    if (OP == OP_PR) {
+        const C om_p = C(1) / r.tau_p;
+        const C om_m = C(1) / r.tau_m;
+        const C ug = p.g[0] * (C(2) * u[0] + p.g[0]) + p.g[1] * (C(2) * u[1] + p.g[1]) +
+                     p.g[2] * (C(2) * u[2] + p.g[2]);
+        {  // rest velocity: symmetric only
+            const C w = C(L::w[0]);
+            const C es = w * (mo.drho - C(1.5) * r.rho * uu);
+            h[0] = h[0] - om_p * (h[0] - es) - C(1.5) * r.rho * w * ug;
+        }
+#pragma unroll
+        for (int i = 1; i < L::Q; i += 2) {
+            const int k = i + 1;
+            const C w = C(L::w[i]);
+            C cu = 0, cg = 0;
+            add_c<LAT>(cu, u[0], L::cx[i]);
+            add_c<LAT>(cu, u[1], L::cy[i]);
+            add_c<LAT>(cu, u[2], L::cz[i]);
+            add_c<LAT>(cg, p.g[0], L::cx[i]);
+            add_c<LAT>(cg, p.g[1], L::cy[i]);
+            add_c<LAT>(cg, p.g[2], L::cz[i]);
+            const C es = w * (mo.drho + r.rho * (C(4.5) * cu * cu - C(1.5) * uu));
+            const C ea = C(3) * w * r.rho * cu;
+            const C hs = C(0.5) * (h[i] + h[k]);
+            const C ha = C(0.5) * (h[i] - h[k]);
+            const C ns = om_p * (hs - es);
+            const C na = om_m * (ha - ea);
+            // f_eq(u+g) - f_eq(u) for +c and -c
+            const C fs = r.rho * w * (C(4.5) * cg * (C(2) * cu + cg) - C(1.5) * ug);
+            const C fa = r.rho * w * C(3) * cg;
+            h[i] = h[i] - ns - na + fs + fa;
+            h[k] = h[k] - ns + na + fs - fa;
+        }
+    } else {
+        const C* A = r.a;
+        const C trA = A[0] + A[1] + A[2];
+        const C third = C(1) / C(3);
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i) {
+            const C w = C(L::w[i]);
+            C cu = 0, cg = 0;
+            add_c<LAT>(cu, u[0], L::cx[i]);
+            add_c<LAT>(cu, u[1], L::cy[i]);
+            add_c<LAT>(cu, u[2], L::cz[i]);
+            add_c<LAT>(cg, p.g[0], L::cx[i]);
+            add_c<LAT>(cg, p.g[1], L::cy[i]);
+            add_c<LAT>(cg, p.g[2], L::cz[i]);
+            C cac = 0;
+            add_c<LAT>(cac, A[0], L::cx[i] * L::cx[i]);
+            add_c<LAT>(cac, A[1], L::cy[i] * L::cy[i]);
+            add_c<LAT>(cac, A[2], L::cz[i] * L::cz[i]);
+            add_c<LAT>(cac, C(2) * A[3], L::cx[i] * L::cy[i]);
+            add_c<LAT>(cac, C(2) * A[4], L::cx[i] * L::cz[i]);
+            add_c<LAT>(cac, C(2) * A[5], L::cy[i] * L::cz[i]);
+            const C heq = w * (mo.drho + r.rho * (C(3) * cu + C(4.5) * cu * cu - C(1.5) * uu));
+            h[i] = heq + C(4.5) * w * (cac - trA * third) + C(1.5) * w * r.rho * cg;
+        }
+    }
+}
+
+// Reported velocity j/rho + g/2 (both operators).
+template <class C>
+__device__ __forceinline__ void out_velocity(const Moments<C>& mo, const Pre<C>& r, const Coll<C>& p, C (&uo)[3])
+{
+    const C irho = C(1) / r.rho;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) uo[a] = mo.j[a] * irho + C(0.5) * p.g[a];
+}
+
+}  // namespace lbm

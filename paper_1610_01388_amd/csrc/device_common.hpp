@@ -1,0 +1,80 @@
+// device_common.hpp -- storage codec and small device helpers shared by the
+// step kernel and the node-range kernels (internal).
+#pragma once
+
+#include "kernels.hpp"
+
+namespace lbm {
+
+template <int PREC> struct Store;
+template <> struct Store<PREC_F64> { using S = double; using C = double; using T = double; };
+template <> struct Store<PREC_F32> { using S = float; using C = float; using T = float; };
+template <> struct Store<PREC_F16> { using S = _Float16; using C = float; using T = float; };
+
+template <class C> __device__ __forceinline__ const Coll<C>& coll_of(const StepArgs& a);
+template <> __device__ __forceinline__ const Coll<double>& coll_of<double>(const StepArgs& a) { return a.cd; }
+template <> __device__ __forceinline__ const Coll<float>& coll_of<float>(const StepArgs& a) { return a.cf; }
+
+// Storage codec.  FP64/FP32 hold h = f - w rho0 directly; FP16 holds
+// h * 2^k / w (round to nearest even), decoded to float.
+template <int PREC>
+__device__ __forceinline__ typename Store<PREC>::C decode(typename Store<PREC>::S v, double w, float scale)
+{
+    if constexpr (PREC == PREC_F16) return (float)v * ((float)w * scale);
+    else return v;
+}
+
+template <int PREC>
+__device__ __forceinline__ typename Store<PREC>::S encode(typename Store<PREC>::C h, double w, float inv)
+{
+    if constexpr (PREC == PREC_F16) return (_Float16)(h * ((float)(1.0 / w) * inv));
+    else return h;
+}
+
+// Wrap a halo coordinate g in [-1, n]: periodic axes wrap, walls give
+// "outside" (treated as solid: halfway bounce-back at the face).
+__device__ __forceinline__ int wrap_halo(int g, int n, int per, bool& out)
+{
+    if (g < 0) {
+        if (per) return g + n;
+        out = true;
+        return 0;
+    }
+    if (g >= n) {
+        if (per && g == n) return 0;
+        out = true;
+        return 0;
+    }
+    return g;
+}
+
+template <int N>
+__device__ __forceinline__ void block_reduce_store(double (&v)[N], double* dst)
+{
+    __shared__ double red[4][N];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            const double o = __shfl_xor(v[k], off, 64);
+            v[k] = (k == MP_UMAX) ? fmax(v[k], o) : v[k] + o;
+        }
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) red[wave][k] = v[k];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int nw = (blockDim.x + 63) >> 6;
+        for (int k = 0; k < N; ++k) {
+            double s = red[0][k];
+            for (int w = 1; w < nw; ++w) s = (k == MP_UMAX) ? fmax(s, red[w][k]) : s + red[w][k];
+            dst[k] = s;
+        }
+    }
+}
+
+}  // namespace lbm

@@ -1,0 +1,98 @@
+// kernels.hpp -- launch arguments shared by the device kernels and the host
+// library (internal; not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "collide.hpp"
+
+namespace lbm {
+
+// Streaming patterns.
+//  PAT_AB:        read the post-collision array A by pulling (x - c_i, or the
+//                 node's own opposite slot when x - c_i is solid / a wall),
+//                 write post-collision values to B at x.
+//  PAT_AA_PULL:   AA step on a state stored "swapped" (P_i(x) in slot
+//                 opp(i) at x): pull as above from the swapped slots,
+//                 collide, push P_i(x) to slot i at x + c_i (or to slot
+//                 opp(i) at x when x + c_i is solid): leaves streamed,
+//                 pre-collision values in natural slots.
+//  PAT_AA_LOCAL:  AA step on a streamed state in natural slots: read slot i
+//                 at x, collide, write P_i(x) to slot opp(i) at x.
+enum { PAT_AB = 0, PAT_AA_PULL = 1, PAT_AA_LOCAL = 2 };
+enum { PREC_F64 = 0, PREC_F32 = 1, PREC_F16 = 2 };
+
+// Per-block monitor partial sums (doubles, fixed order).
+enum { MP_UX = 0, MP_UY, MP_UZ, MP_MASS, MP_UMAX, MP_UNYIELDED, MP_FALLBACK, MP_NONFINITE, MP_FLUID, MP_COUNT };
+
+// Population storage layouts.
+//  LAYOUT_DENSE:   every node has a slot; slot (i, n) at i*S + n with S = N;
+//                  solid mask as one byte per node.
+//  LAYOUT_COMPACT: only fluid nodes have slots, numbered in node order
+//                  (x fastest); slot (i, k) at i*S + k with S = fluid count
+//                  rounded up to 64.  The mask is a bitmap per row (y, z):
+//                  W = ceil(nx/64) 64-bit words per row, bit x%64 of word
+//                  x/64 set for fluid, and wbase[row][word] = compact index
+//                  of the first fluid node at or after x = 64*word, so
+//                  k(x) = wbase + popcount(bits below x).
+enum { LAYOUT_COMPACT = 0, LAYOUT_DENSE = 1 };  // same values as lbm_layout
+
+struct StepArgs {
+    const void* src;       // populations read
+    void* dst;             // populations written (== src for AA)
+    void* tau;             // PR relaxation time (double for FP64, float otherwise), in place
+    const uint8_t* mask;   // dense: 1 = solid
+    const uint64_t* bits;  // compact: fluid bitmap [row][W]
+    const uint32_t* wbase; // compact: [row][W]
+    double* partials;      // MON: MP_COUNT doubles per tile
+    int64_t N;             // nodes
+    int64_t S;             // direction stride of the population arrays
+    int W;                 // compact: words per row
+    int nx, ny, nz;
+    int per[3];
+    int tx, ty, tz;        // tile shape (threads per block = tx*ty*tz)
+    int ntx, nty, ntz;     // tiles per axis
+    int ntiles;
+    int tiles_per_xcd;     // ceil(ntiles / 8): tiles handed to each XCD as one contiguous range
+    int fallback;          // reduced precision: FP64 redo of near-yield nodes
+    float h16_scale;       // FP16: 2^-k  (h = half * w * 2^-k)
+    float h16_inv;         // FP16: 2^k
+    Coll<double> cd;
+    Coll<float> cf;
+};
+
+// Node-range kernels (readout, monitors on demand, population IO, init).
+struct NodeArgs {
+    void* pdf;             // population array (AB: the current post-collision copy)
+    void* tau;
+    const uint8_t* mask;
+    const uint64_t* bits;
+    const uint32_t* wbase;
+    int64_t S;             // direction stride
+    int W;
+    int compact;
+    double* partials;      // monitors on demand
+    double* out;           // staging (layout depends on the kernel)
+    uint8_t* out_flags;
+    int64_t N, n0, count;  // nodes [n0, n0 + count)
+    int nx, ny, nz;
+    int per[3];
+    int layout;            // 0: post-collision natural, 1: post-collision swapped (AA), 2: streamed natural (AA)
+    int reduce;            // monitors: write per-block partials instead of per-node outputs
+    float h16_scale, h16_inv;
+    double u0[3];
+    Coll<double> cd;
+    Coll<float> cf;
+};
+
+hipError_t launch_step(int lat, int op, int prec, int pat, bool mon, int layout, const StepArgs& a, hipStream_t s);
+hipError_t launch_finalize(const double* partials, int64_t nparts, void* record, int64_t step, double ntotal,
+                           hipStream_t s);
+hipError_t launch_init(int lat, int op, int prec, const NodeArgs& a, double rho0, hipStream_t s);
+hipError_t launch_readout(int lat, int op, int prec, const NodeArgs& a, hipStream_t s, int64_t* nblocks);
+hipError_t launch_pop_write(int lat, int prec, const NodeArgs& a, hipStream_t s);
+hipError_t launch_pop_read(int lat, int prec, const NodeArgs& a, hipStream_t s);
+hipError_t launch_fill_u8(uint8_t* p, int64_t n, uint8_t v, hipStream_t s);
+
+}  // namespace lbm

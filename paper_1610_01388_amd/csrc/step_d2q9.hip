@@ -1,0 +1,6 @@
+// step_d2q9.hip -- stream-collide kernel instantiations for one lattice.
+#include "step_impl.hpp"
+
+namespace lbm {
+template hipError_t launch_step_lattice<0>(int, int, int, bool, int, const StepArgs&, hipStream_t);
+}

@@ -1,0 +1,400 @@
+// step_impl.hpp -- the fused stream-collide kernel (one time step), included
+// by one translation unit per lattice so that the instantiations compile in
+// parallel.
+//
+// One thread updates one node.  A block owns a tx*ty*tz tile; the solid mask
+// of the tile plus a one-node halo is staged in LDS, so the 2Q neighbour
+// tests of streaming and bounce-back are LDS reads.  Populations are SoA
+// ([i][n], x fastest): for a fixed direction the lanes of a wavefront read
+// and write consecutive addresses.  Block b is given tile
+// (b mod 8) * tiles_per_xcd + b / 8: consecutive workgroups go to different
+// XCDs, so this hands each XCD one contiguous slab of tiles and keeps the
+// halo reuse between neighbouring tiles inside one XCD's L2.
+#pragma once
+
+#include "device_common.hpp"
+
+namespace lbm {
+
+// Collision of one node on its pre-collision deviations h (in place), with
+// the FP64 redo of near-yield nodes in reduced precision.
+template <int LAT, int OP, int PREC>
+__device__ __forceinline__ void collide_node(typename Store<PREC>::C (&h)[Lattice<LAT>::Q],
+                                             typename Store<PREC>::C tau_prev, const StepArgs& a,
+                                             Moments<typename Store<PREC>::C>& mo,
+                                             Pre<typename Store<PREC>::C>& pr, bool& used_fb)
+{
+    using C = typename Store<PREC>::C;
+    constexpr int Q = Lattice<LAT>::Q;
+    const Coll<C>& cp = coll_of<C>(a);
+    mo = moments<LAT>(h);
+    pr = rheology<LAT, OP>(mo, cp, tau_prev);
+    if constexpr (PREC != PREC_F64) {
+        if (a.fallback && pr.near_yield) {
+            double hd[Q];
+#pragma unroll
+            for (int i = 0; i < Q; ++i) hd[i] = (double)h[i];
+            const Moments<double> md = moments<LAT>(hd);
+            const Pre<double> pd = rheology<LAT, OP>(md, a.cd, (double)tau_prev);
+            relax<LAT, OP>(hd, md, pd, a.cd);
+#pragma unroll
+            for (int i = 0; i < Q; ++i) h[i] = (C)hd[i];
+            pr.tau_p = (C)pd.tau_p;
+            pr.unyielded = pd.unyielded;
+            used_fb = true;
+            return;
+        }
+    }
+    relax<LAT, OP>(h, mo, pr, cp);
+}
+
+// Per-block monitor partial sums of the state the step started from.
+template <class C>
+__device__ __forceinline__ void monitor_block(bool active, const Moments<C>& mo, const Pre<C>& pr,
+                                              const Coll<C>& cp, bool used_fb, double* dst)
+{
+    double v[MP_COUNT];
+#pragma unroll
+    for (int k = 0; k < MP_COUNT; ++k) v[k] = 0.0;
+    if (active) {
+        C uo[3];
+        out_velocity(mo, pr, cp, uo);
+        const double ux = uo[0], uy = uo[1], uz = uo[2], rho = pr.rho;
+        const bool bad = !isfinite(rho) || !isfinite(ux) || !isfinite(uy) || !isfinite(uz);
+        v[MP_UX] = ux;
+        v[MP_UY] = uy;
+        v[MP_UZ] = uz;
+        v[MP_MASS] = rho;
+        v[MP_UMAX] = bad ? INFINITY : sqrt(ux * ux + uy * uy + uz * uz);
+        v[MP_UNYIELDED] = pr.unyielded ? 1.0 : 0.0;
+        v[MP_FALLBACK] = used_fb ? 1.0 : 0.0;
+        v[MP_NONFINITE] = bad ? 1.0 : 0.0;
+        v[MP_FLUID] = 1.0;
+    }
+    block_reduce_store<MP_COUNT>(v, dst);
+}
+
+template <int LAT, int OP, int PREC, int PAT, bool MON>
+__global__ __launch_bounds__(256) void k_step(const StepArgs a)
+{
+    using L = Lattice<LAT>;
+    constexpr int Q = L::Q;
+    constexpr int D = L::D;
+    using S = typename Store<PREC>::S;
+    using C = typename Store<PREC>::C;
+    using T = typename Store<PREC>::T;
+    constexpr bool PULLS = (PAT != PAT_AA_LOCAL);
+    extern __shared__ uint8_t halo[];
+
+    const int b = blockIdx.x;
+    const int tile = (b & 7) * a.tiles_per_xcd + (b >> 3);
+    if (tile >= a.ntiles) return;  // whole block leaves together
+
+    const int t = threadIdx.x;
+    const int lx = t % a.tx;
+    const int lyz = t / a.tx;
+    const int ly = lyz % a.ty;
+    const int lz = lyz / a.ty;
+    const int ttx = tile % a.ntx;
+    const int trem = tile / a.ntx;
+    const int tty = trem % a.nty;
+    const int ttz = trem / a.nty;
+    const int x = ttx * a.tx + lx;
+    const int y = tty * a.ty + ly;
+    const int z = ttz * a.tz + lz;
+    const bool inside = (x < a.nx) & (y < a.ny) & (z < a.nz);
+    const int64_t N = a.S;  // direction stride (= node count, dense layout)
+    const int64_t n = x + (int64_t)a.nx * (y + (int64_t)a.ny * z);
+
+    const int hx = a.tx + 2;
+    const int hy = a.ty + 2;
+    const int hc = (lx + 1) + hx * ((ly + 1) + hy * ((D == 3) ? lz + 1 : 0));
+    if constexpr (PULLS) {
+        const int hz = (D == 3) ? a.tz + 2 : 1;
+        const int hn = hx * hy * hz;
+        const int x0 = ttx * a.tx - 1, y0 = tty * a.ty - 1, z0 = (D == 3) ? ttz * a.tz - 1 : 0;
+        for (int k = t; k < hn; k += blockDim.x) {
+            const int kx = k % hx;
+            const int kr = k / hx;
+            const int ky = kr % hy;
+            const int kz = kr / hy;
+            bool out = false;
+            const int gx = wrap_halo(x0 + kx, a.nx, a.per[0], out);
+            const int gy = wrap_halo(y0 + ky, a.ny, a.per[1], out);
+            const int gz = (D == 3) ? wrap_halo(z0 + kz, a.nz, a.per[2], out) : 0;
+            halo[k] = out ? (uint8_t)1 : a.mask[gx + (int64_t)a.nx * (gy + (int64_t)a.ny * gz)];
+        }
+        __syncthreads();
+    }
+    bool solid = true;
+    if (inside) solid = PULLS ? (halo[hc] != 0) : (a.mask[n] != 0);
+    const bool active = inside && !solid;
+
+    // wrapped neighbour coordinates (only used where the neighbour is fluid)
+    const int xm = (x == 0) ? a.nx - 1 : x - 1, xp = (x == a.nx - 1) ? 0 : x + 1;
+    const int ym = (y == 0) ? a.ny - 1 : y - 1, yp = (y == a.ny - 1) ? 0 : y + 1;
+    const int zm = (z == 0) ? a.nz - 1 : z - 1, zp = (z == a.nz - 1) ? 0 : z + 1;
+
+    C h[Q];
+    C tau_prev = C(0);
+    const Coll<C>& cp = coll_of<C>(a);
+    Moments<C> mo;
+    Pre<C> pr;
+    bool used_fb = false;
+    if (active) {
+        const S* A = (const S*)a.src;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const int cx = L::cx[i], cy = L::cy[i], cz = L::cz[i];
+            int64_t idx;
+            if constexpr (PAT == PAT_AA_LOCAL) {
+                idx = (int64_t)i * N + n;
+            } else {
+                const bool sb = halo[hc - cx - hx * (cy + hy * cz)] != 0;
+                const int sx = cx == 0 ? x : (cx > 0 ? xm : xp);
+                const int sy = cy == 0 ? y : (cy > 0 ? ym : yp);
+                const int sz = cz == 0 ? z : (cz > 0 ? zm : zp);
+                const int64_t ns = sx + (int64_t)a.nx * (sy + (int64_t)a.ny * sz);
+                if constexpr (PAT == PAT_AB)
+                    idx = sb ? (int64_t)opp(i) * N + n : (int64_t)i * N + ns;
+                else
+                    idx = sb ? (int64_t)i * N + n : (int64_t)opp(i) * N + ns;
+            }
+            h[i] = decode<PREC>(A[idx], L::w[i], a.h16_scale);
+        }
+        if constexpr (OP == OP_PR) tau_prev = (C)((const T*)a.tau)[n];
+
+        collide_node<LAT, OP, PREC>(h, tau_prev, a, mo, pr, used_fb);
+
+        S* B = (S*)a.dst;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const int cx = L::cx[i], cy = L::cy[i], cz = L::cz[i];
+            int64_t idx;
+            if constexpr (PAT == PAT_AB) {
+                idx = (int64_t)i * N + n;
+            } else if constexpr (PAT == PAT_AA_LOCAL) {
+                idx = (int64_t)opp(i) * N + n;
+            } else {
+                const bool sd = halo[hc + cx + hx * (cy + hy * cz)] != 0;
+                const int dx = cx == 0 ? x : (cx > 0 ? xp : xm);
+                const int dy = cy == 0 ? y : (cy > 0 ? yp : ym);
+                const int dz = cz == 0 ? z : (cz > 0 ? zp : zm);
+                const int64_t nd = dx + (int64_t)a.nx * (dy + (int64_t)a.ny * dz);
+                idx = sd ? (int64_t)opp(i) * N + n : (int64_t)i * N + nd;
+            }
+            B[idx] = encode<PREC>(h[i], L::w[i], a.h16_inv);
+        }
+        if constexpr (OP == OP_PR) ((T*)a.tau)[n] = (T)pr.tau_p;
+    }
+
+    if constexpr (MON) monitor_block<C>(active, mo, pr, cp, used_fb, a.partials + (int64_t)tile * MP_COUNT);
+}
+
+// Compact-layout step: only fluid nodes have population slots.  A wavefront
+// is one 64-node segment of one row (y, z): block = 64 x ty x tz, one wave per
+// row segment.  For each of the 3 (2-D) or 9 (3-D) rows around it, the
+// segment's bitmap word and the words holding its left and right neighbours
+// are wave-uniform, so they are read once per wave; each lane then gets the
+// fluid flag and compact index of its x-1, x, x+1 neighbours in that row from
+// the word's rank below the lane (mbcnt) and single-bit tests.
+template <int LAT, int OP, int PREC, int PAT, bool MON>
+__global__ __launch_bounds__(256) void k_step_compact(const StepArgs a, const uint64_t* __restrict__ bits,
+                                                      const uint32_t* __restrict__ wbase)
+{
+    using L = Lattice<LAT>;
+    constexpr int Q = L::Q;
+    constexpr int D = L::D;
+    using S = typename Store<PREC>::S;
+    using C = typename Store<PREC>::C;
+    using T = typename Store<PREC>::T;
+
+    const int b = blockIdx.x;
+    const int tile = (b & 7) * a.tiles_per_xcd + (b >> 3);
+    if (tile >= a.ntiles) return;  // whole block leaves together
+
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int ly = wv % a.ty;
+    const int lz = wv / a.ty;
+    const int ttx = tile % a.ntx;
+    const int trem = tile / a.ntx;
+    const int tty = trem % a.nty;
+    const int ttz = trem / a.nty;
+    const int x0 = ttx * 64;
+    const int x = x0 + lane;
+    const int y = tty * a.ty + ly;
+    const int z = ttz * a.tz + lz;
+    const bool wave_in = (y < a.ny) && (z < a.nz);
+    const int64_t St = a.S;
+
+    // neighbourhood: fluid flag (bit d) and compact index of node x + d,
+    // d = (dx, dy, dz) in {-1,0,1}^3, index (dx+1) + 3 (dy+1) + 9 (dz+1)
+    uint32_t nbf = 0;
+    uint32_t nbi[27];
+#pragma unroll
+    for (int k = 0; k < 27; ++k) nbi[k] = 0;
+#pragma unroll
+    for (int dz = -1; dz <= 1; ++dz) {
+        if (D == 2 && dz != 0) continue;
+#pragma unroll
+        for (int dy = -1; dy <= 1; ++dy) {
+            bool rv = wave_in;
+            int yy = y + dy, zz = z + dz;
+            if (yy < 0 || yy >= a.ny) {
+                if (a.per[1]) yy = (yy + a.ny) % a.ny;
+                else rv = false;
+            }
+            if (zz < 0 || zz >= a.nz) {
+                if (a.per[2]) zz = (zz + a.nz) % a.nz;
+                else rv = false;
+            }
+            uint64_t mb = 0, lb = 0, rb = 0;
+            uint32_t mbase = 0, li = 0, ri = 0;
+            bool lf = false, rf = false;
+            if (rv) {
+                const int64_t row = ((int64_t)yy + (int64_t)a.ny * zz) * a.W;
+                mb = bits[row + ttx];
+                mbase = wbase[row + ttx];
+                int wl = -1, bl = 63;
+                if (x0 > 0) wl = ttx - 1;
+                else if (a.per[0]) { wl = (a.nx - 1) >> 6; bl = (a.nx - 1) & 63; }
+                if (wl >= 0) {
+                    lb = bits[row + wl];
+                    lf = (lb >> bl) & 1;
+                    li = wbase[row + wl] + (uint32_t)__popcll(lb & ((1ull << bl) - 1ull));
+                }
+                int wr = -1;
+                if (x0 + 64 < a.nx) wr = ttx + 1;
+                else if (a.per[0]) wr = 0;
+                if (wr >= 0) {
+                    rb = bits[row + wr];
+                    rf = rb & 1;
+                    ri = wbase[row + wr];
+                }
+            }
+            const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(mb >> 32),
+                                                            __builtin_amdgcn_mbcnt_lo((uint32_t)mb, 0u));
+            const bool fm = (mb >> lane) & 1;
+            const uint32_t im = mbase + rank;
+            bool fL;
+            uint32_t iL;
+            if (lane > 0) { fL = (mb >> (lane - 1)) & 1; iL = im - 1; }
+            else { fL = lf; iL = li; }
+            const bool last = (lane == 63) || (x == a.nx - 1);
+            bool fR;
+            uint32_t iR;
+            if (!last) { fR = (mb >> (lane + 1)) & 1; iR = im + (fm ? 1u : 0u); }
+            else { fR = rf; iR = ri; }
+            const int base = 3 * (dy + 1) + 9 * (dz + 1);
+            nbf |= (fL ? 1u : 0u) << (base + 0);
+            nbf |= (fm ? 1u : 0u) << (base + 1);
+            nbf |= (fR ? 1u : 0u) << (base + 2);
+            nbi[base + 0] = iL;
+            nbi[base + 1] = im;
+            nbi[base + 2] = iR;
+        }
+    }
+    constexpr int SELF = 13;
+    const bool active = wave_in && ((nbf >> SELF) & 1);
+    const int64_t k = nbi[SELF];
+
+    C h[Q];
+    C tau_prev = C(0);
+    const Coll<C>& cp = coll_of<C>(a);
+    Moments<C> mo;
+    Pre<C> pr;
+    bool used_fb = false;
+    if (active) {
+        const S* A = (const S*)a.src;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            int64_t idx;
+            if constexpr (PAT == PAT_AA_LOCAL) {
+                idx = (int64_t)i * St + k;
+            } else {
+                const int d = (1 - L::cx[i]) + 3 * (1 - L::cy[i]) + 9 * (1 - L::cz[i]);  // x - c_i
+                const bool fl = (nbf >> d) & 1;
+                if constexpr (PAT == PAT_AB)
+                    idx = fl ? (int64_t)i * St + nbi[d] : (int64_t)opp(i) * St + k;
+                else
+                    idx = fl ? (int64_t)opp(i) * St + nbi[d] : (int64_t)i * St + k;
+            }
+            h[i] = decode<PREC>(A[idx], L::w[i], a.h16_scale);
+        }
+        if constexpr (OP == OP_PR) tau_prev = (C)((const T*)a.tau)[k];
+
+        collide_node<LAT, OP, PREC>(h, tau_prev, a, mo, pr, used_fb);
+
+        S* B = (S*)a.dst;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            int64_t idx;
+            if constexpr (PAT == PAT_AB) {
+                idx = (int64_t)i * St + k;
+            } else if constexpr (PAT == PAT_AA_LOCAL) {
+                idx = (int64_t)opp(i) * St + k;
+            } else {
+                const int d = (1 + L::cx[i]) + 3 * (1 + L::cy[i]) + 9 * (1 + L::cz[i]);  // x + c_i
+                const bool fl = (nbf >> d) & 1;
+                idx = fl ? (int64_t)i * St + nbi[d] : (int64_t)opp(i) * St + k;
+            }
+            B[idx] = encode<PREC>(h[i], L::w[i], a.h16_inv);
+        }
+        if constexpr (OP == OP_PR) ((T*)a.tau)[k] = (T)pr.tau_p;
+    }
+    if constexpr (MON) monitor_block<C>(active, mo, pr, cp, used_fb, a.partials + (int64_t)tile * MP_COUNT);
+}
+
+template <int LAT, int OP, int PREC, int PAT, bool MON>
+static hipError_t go_step(int layout, const StepArgs& a, hipStream_t s)
+{
+    const int threads = a.tx * a.ty * a.tz;
+    const dim3 grid(8 * a.tiles_per_xcd);
+    if (layout == LAYOUT_COMPACT) {
+        hipLaunchKernelGGL((k_step_compact<LAT, OP, PREC, PAT, MON>), grid, dim3(threads), 0, s, a, a.bits, a.wbase);
+    } else {
+        const int hz = (Lattice<LAT>::D == 3) ? a.tz + 2 : 1;
+        const size_t sh = (PAT != PAT_AA_LOCAL) ? (size_t)(a.tx + 2) * (a.ty + 2) * hz : 0;
+        hipLaunchKernelGGL((k_step<LAT, OP, PREC, PAT, MON>), grid, dim3(threads), sh, s, a);
+    }
+    return hipGetLastError();
+}
+
+template <int LAT, int OP, int PREC>
+static hipError_t go_pat(int pat, bool mon, int layout, const StepArgs& a, hipStream_t s)
+{
+    switch (pat) {
+    case PAT_AB:
+        return mon ? go_step<LAT, OP, PREC, PAT_AB, true>(layout, a, s)
+                   : go_step<LAT, OP, PREC, PAT_AB, false>(layout, a, s);
+    case PAT_AA_PULL:
+        return mon ? go_step<LAT, OP, PREC, PAT_AA_PULL, true>(layout, a, s)
+                   : go_step<LAT, OP, PREC, PAT_AA_PULL, false>(layout, a, s);
+    case PAT_AA_LOCAL:
+        return mon ? go_step<LAT, OP, PREC, PAT_AA_LOCAL, true>(layout, a, s)
+                   : go_step<LAT, OP, PREC, PAT_AA_LOCAL, false>(layout, a, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <int LAT>
+hipError_t launch_step_lattice(int op, int prec, int pat, bool mon, int layout, const StepArgs& a, hipStream_t s)
+{
+    if (op == OP_PR) {
+        switch (prec) {
+        case PREC_F64: return go_pat<LAT, OP_PR, PREC_F64>(pat, mon, layout, a, s);
+        case PREC_F32: return go_pat<LAT, OP_PR, PREC_F32>(pat, mon, layout, a, s);
+        case PREC_F16: return go_pat<LAT, OP_PR, PREC_F16>(pat, mon, layout, a, s);
+        }
+    } else {
+        switch (prec) {
+        case PREC_F64: return go_pat<LAT, OP_IR, PREC_F64>(pat, mon, layout, a, s);
+        case PREC_F32: return go_pat<LAT, OP_IR, PREC_F32>(pat, mon, layout, a, s);
+        case PREC_F16: return go_pat<LAT, OP_IR, PREC_F16>(pat, mon, layout, a, s);
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace lbm
