@@ -64,8 +64,7 @@ def make_domain(lbm, case, precision, scheme="AA", mask=None, **kw):
     dom = lbm.Domain(case["lattice"], case["dims"], case["periodic"], case["op"], case["nu_p"],
                      case["sigma_y"], m=case["m"], g=case["g"], precision=precision, scheme=scheme, **kw)
     if mask is not None:
-        dom.set_mask(mask)
-        dom.init()
+        dom.set_mask(mask)  # also resets the state to rest
     return dom
 
 
@@ -86,12 +85,13 @@ def timed_run(torch, dom, warmup, steps, mon_every=100):
     return ms, wall
 
 
-def compare(ref, got, fluid):
-    """Velocity L2-rel, flux rel, plug volume (unyielded count) rel."""
+def compare(ref, got, axis):
+    """Velocity L2-rel, flux rel (along the force axis), plug volume
+    (unyielded count) rel."""
     rho_r, u_r, _, uy_r = ref
     rho_g, u_g, _, uy_g = got
     l2 = float(np.linalg.norm(u_g - u_r) / max(np.linalg.norm(u_r), 1e-300))
-    fr, fg = u_r[0].sum(), u_g[0].sum()
+    fr, fg = u_r[axis].sum(), u_g[axis].sum()
     flux_rel = float(abs(fg - fr) / max(abs(fr), 1e-300))
     pr, pg = int(uy_r.sum()), int(uy_g.sum())
     plug_rel = float(abs(pg - pr) / max(pr, 1))
@@ -116,7 +116,7 @@ def run_form(torch, lbm, name, case, precision, mask, fluid, warmup, steps, ref=
                                "fallback_nodes": int(hist[-1]["fallback"]),
                                "unyielded": int(hist[-1]["unyielded"])}
     if ref is not None:
-        out["error_vs_fp64"] = compare(ref, mom, fluid)
+        out["error_vs_fp64"] = compare(ref, mom, int(np.argmax(np.abs(case["g"]))))
     dom.close()
     torch.cuda.empty_cache()
     return out, mom
@@ -163,6 +163,8 @@ def main():
     ap.add_argument("--size", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-forms", action="store_true", help="main line only")
+    ap.add_argument("--layout", default="COMPACT", choices=["COMPACT", "DENSE"],
+                    help="population storage layout of the main line")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a 1 GiB device copy first (counter calibration under rocprofv3)")
     args = ap.parse_args()
@@ -194,8 +196,8 @@ def main():
     case = inputs.porous_case("IR", n=n, Bi=1.0)
     case_pr = inputs.porous_case("PR", n=n, Bi=1.0, m=1e4)
 
-    log(f"main: D3Q27 {n}^3 IR FP64 AA, warmup {args.warmup}, steps {args.steps}")
-    dom = make_domain(lbm, case, "FP64", mask=mask)
+    log(f"main: D3Q27 {n}^3 IR FP64 AA {args.layout}, warmup {args.warmup}, steps {args.steps}")
+    dom = make_domain(lbm, case, "FP64", mask=mask, layout=args.layout)
     tile = dom.tile()
     ms, wall = timed_run(torch, dom, args.warmup, args.steps)
     ref_ir = dom.moments()
@@ -208,7 +210,7 @@ def main():
     per_launch = fluid * bpn
     achieved = per_launch / (ms_step * 1e-3) / 1e9
     khash = kernel_source_hash()
-    traffic = traffic_from_profile(khash, per_launch)
+    traffic = traffic_from_profile(khash, per_launch) if args.layout == "COMPACT" else None
     log(f"  {ms_step:.3f} ms/step, {mlups:.1f} MLUPS, {achieved:.0f} GB/s algorithmic")
 
     result = {
@@ -216,8 +218,10 @@ def main():
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"D3Q27 periodic {n}^3 random sphere pack (R=8, porosity 0.7, seed 1), "
-                               "IR Bingham operator, Bi=1, FP64, AA in-place streaming",
+                               "IR Bingham operator, Bi=1, FP64, AA in-place streaming, "
+                               f"{args.layout.lower()} layout",
                    "lattice": "D3Q27", "operator": "IR", "precision": "FP64", "scheme": "AA",
+                   "layout": args.layout,
                    "dims": [n, n, n], "fluid_nodes": fluid, "porosity": float(1 - mask.mean()),
                    "nu_p": case["nu_p"], "sigma_y": case["sigma_y"], "g": list(case["g"]),
                    "tile": list(tile), "monitor_every": 100,
@@ -225,7 +229,9 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "algorithmic_bytes_per_launch": per_launch, "bytes_per_fluid_node": bpn,
-                     "kernel": "k_step<D3Q27, IR, FP64, AA pull/local>", "kernel_source_hash": khash},
+                     "kernel": f"k_step{'_compact' if args.layout == 'COMPACT' else ''}<D3Q27, IR, FP64, "
+                               "AA pull/local> (mean of the two alternating AA phases)",
+                     "kernel_source_hash": khash},
     }
     if hist:
         result["config"]["last_monitor"] = {"step": hist[-1]["step"], "flux": float(hist[-1]["flux"][0]),
@@ -235,21 +241,32 @@ def main():
     forms = []
     if not args.no_forms:
         W, K = args.warmup, min(args.steps, 500)
-        ref_steps_ir = None
-        # FP64 references at W+K steps for the error statements
-        log("forms: FP64 references")
+        log("forms: FP64 references (compact layout) and the dense layout")
         f64_ir, ref_ir = run_form(torch, lbm, "IR FP64", case, "FP64", mask, fluid, W, K)
         f64_pr, ref_pr = run_form(torch, lbm, "PR FP64", case_pr, "FP64", mask, fluid, W, K)
-        forms += [f64_ir, f64_pr]
-        log("forms: FP32")
+        dense_ir, _ = run_form(torch, lbm, "IR FP64 dense layout", case, "FP64", mask, fluid, W, K, ref=ref_ir,
+                               layout="DENSE")
+        forms += [f64_ir, f64_pr, dense_ir]
+        log("forms: FP32 storage and collision")
         forms.append(run_form(torch, lbm, "IR FP32", case, "FP32", mask, fluid, W, K, ref=ref_ir)[0])
         forms.append(run_form(torch, lbm, "PR FP32", case_pr, "FP32", mask, fluid, W, K, ref=ref_pr)[0])
-        log("forms: FP16 storage with FP64 fallback")
-        forms.append(run_form(torch, lbm, "IR FP16+fallback", case, "FP16", mask, fluid, W, K, ref=ref_ir,
-                              fp64_fallback=True, fallback_band=0.05, fp16_scale_log2=14)[0])
-        forms.append(run_form(torch, lbm, "PR FP16+fallback", case_pr, "FP16", mask, fluid, W, K, ref=ref_pr,
-                              fp64_fallback=True, fallback_band=1.0, fp16_scale_log2=14)[0])
         del ref_ir, ref_pr
+        n4 = 384 if n == 256 else n
+        log(f"forms: FP16 storage with FP64 fallback, {n4}^3 pack (seed 2)")
+        mask4, _ = inputs.sphere_pack((n4, n4, n4), 8.0, 0.7, seed=2)
+        fl4 = int((mask4 == 0).sum())
+        c4_ir = inputs.porous_case("IR", n=n4, Bi=1.0)
+        c4_pr = inputs.porous_case("PR", n=n4, Bi=1.0, m=1e4)
+        r64, ref4 = run_form(torch, lbm, f"IR FP64 {n4}^3", c4_ir, "FP64", mask4, fl4, W, K)
+        forms.append(r64)
+        forms.append(run_form(torch, lbm, f"IR FP16+fallback {n4}^3", c4_ir, "FP16", mask4, fl4, W, K, ref=ref4,
+                              fp64_fallback=True, fallback_band=0.05, fp16_scale_log2=14)[0])
+        del ref4
+        r64, ref4 = run_form(torch, lbm, f"PR FP64 {n4}^3", c4_pr, "FP64", mask4, fl4, W, K)
+        forms.append(r64)
+        forms.append(run_form(torch, lbm, f"PR FP16+fallback {n4}^3", c4_pr, "FP16", mask4, fl4, W, K, ref=ref4,
+                              fp64_fallback=True, fallback_band=1.0, fp16_scale_log2=14)[0])
+        del ref4, mask4
         log("forms: D3Q19 4x128x128 duct (cache-resident: MLUPS only)")
         duct = inputs.duct_case("IR", side=128, length=4, Bi=0.5)
         dfl = 128 * 128 * 4
