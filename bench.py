@@ -122,6 +122,67 @@ def run_form(torch, lbm, name, case, precision, mask, fluid, warmup, steps, ref=
     return out, mom
 
 
+def run_batch(torch, lbm, cases, precision, warmup, steps, autotune=True, graph_steps=100):
+    """The batched sweep: every case in one batch, stepped by graph replays
+    of one persistent launch per step; tiles picked by the autotuner."""
+    b = lbm.Batch(cases, precision=precision)
+    if autotune:
+        b.autotune(10)
+    b.set_graph_steps(graph_steps)
+    b.set_monitor_interval(100)
+    b.step(warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(b.stream)
+    b.step(steps)
+    e1.record(b.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    moms = [b.moments(k) for k in range(len(cases))]
+    tiles = b.tiles()
+    mons = b.monitors()
+    b.close()
+    torch.cuda.empty_cache()
+    return ms, moms, tiles, mons
+
+
+def batch_form(torch, lbm, cases, warmup, steps):
+    """FP32 batched sweep with its error against the FP64 batch of the same
+    cases (same steps from rest)."""
+    nodes = sum(int(np.prod(c["dims"])) for c in cases)
+    bytes_step = sum(int(np.prod(c["dims"])) * algorithmic_bytes_per_node(c["lattice"], c["op"], "FP32")
+                     for c in cases)
+    ms32, m32, tiles, mons = run_batch(torch, lbm, cases, "FP32", warmup, steps)
+    ms64, m64, _, _ = run_batch(torch, lbm, cases, "FP64", warmup, steps)
+    cat = lambda ms: (np.concatenate([m[0] for m in ms]), np.concatenate([m[1] for m in ms], axis=1), None,
+                      np.concatenate([m[3] for m in ms]))
+    err = compare(cat(m64), cat(m32), 2)
+    # per-simulation flux error over the ducts that still flow in FP64
+    rel = []
+    for a, c in zip(m64, m32):
+        f64, f32 = a[1][2].sum(), c[1][2].sum()
+        if abs(f64) > 1e-12 * a[1].shape[1]:
+            rel.append(abs(f32 - f64) / abs(f64))
+    err["flux_rel_max_per_sim"] = float(max(rel)) if rel else None
+    err["flowing_sims"] = len(rel)
+    shapes = {}
+    for t in tiles:
+        shapes[f"{t[0]}x{t[1]}x{t[2]}"] = shapes.get(f"{t[0]}x{t[1]}x{t[2]}", 0) + 1
+    ops = {}
+    for c in cases:
+        key = c["op"] if c["op"] == "IR" else f"PR m={c['m']:g}"
+        ops[key] = ops.get(key, 0) + 1
+    gbs = bytes_step * steps / (ms32 * 1e-3) / 1e9
+    return {"form": f"batched sweep: {len(cases)} D3Q19 ducts FP32", "lattice": "D3Q19", "precision": "FP32",
+            "simulations": len(cases), "nodes": nodes, "steps": steps, "ms_per_step": ms32 / steps,
+            "MLUPS": nodes * steps / (ms32 * 1e-3) / 1e6, "algorithmic_GBs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS,
+            "algorithmic_bytes_per_step": bytes_step, "graph_steps": 100, "tiles": shapes, "operators": ops,
+            "fp64_batch_MLUPS": nodes * steps / (ms64 * 1e-3) / 1e6,
+            "nonfinite_sims": int(sum(1 for m in mons if m["nonfinite"])),
+            "error_vs_fp64": err}
+
+
 def cpu_baseline(case, mask, fluid):
     """The FP64 oracle (single thread, as it stands) on one step of the
     same workload."""
@@ -163,6 +224,8 @@ def main():
     ap.add_argument("--size", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-forms", action="store_true", help="main line only")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="only the batched sweep form (for profiling its kernel)")
     ap.add_argument("--layout", default="COMPACT", choices=["COMPACT", "DENSE"],
                     help="population storage layout of the main line")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -176,6 +239,11 @@ def main():
     import torch
     from paper_1610_01388_amd import inputs, lbm
     torch.cuda.set_device(0)
+
+    if args.batch_only:
+        log(f"batched sweep only: warmup {args.warmup}, steps {args.steps}")
+        print(json.dumps(batch_form(torch, lbm, inputs.batch_sweep(), args.warmup, args.steps)), flush=True)
+        return
 
     if args.copy_calibration:
         a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
@@ -273,6 +341,8 @@ def main():
         d64, dref = run_form(torch, lbm, "duct D3Q19 IR FP64", duct, "FP64", None, dfl, W, K)
         d32, _ = run_form(torch, lbm, "duct D3Q19 IR FP32", duct, "FP32", None, dfl, W, K, ref=dref)
         forms += [d64, d32]
+        log("forms: batched sweep, 256 D3Q19 ducts (sides 32..160, length 4), FP32 vs FP64")
+        forms.append(batch_form(torch, lbm, inputs.batch_sweep(), W, K))
     result["forms"] = forms
 
     if not args.no_cpu:

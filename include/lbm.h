@@ -201,6 +201,58 @@ int lbm_autotune(lbm_domain* dom, int32_t trial_steps);
 
 int lbm_destroy(lbm_domain* dom);
 
+/* ---------------------------------------------------------------------------
+ * Batched sweep: count independent simulations of uneven size (for example
+ * the square ducts of a Bingham-number sweep, Sec. 4.3) advanced together.
+ * Every simulation is all-fluid inside its box (walls only through
+ * non-periodic axes) and has its own sizes, operator and rheology; all
+ * share one lattice, one precision, the AA scheme, the FP64-fallback flag
+ * and the FP16 scale.  One step is one persistent kernel launch over a work
+ * list of 256-node tiles of all simulations; lbm_batch_step replays a
+ * captured hipGraph of graph_steps such launches when it can.  The update
+ * of each node is the same as lbm_step's (a simulation gives bitwise the
+ * same state batched or alone).
+ * ------------------------------------------------------------------------- */
+typedef struct lbm_batch lbm_batch;
+
+/* Device bytes for the arena (pdf), relaxation times (tau, 0 without PR)
+ * and the work buffer (parameter table, work list, monitors, staging);
+ * mask_bytes is 0. */
+int lbm_batch_query_sizes(const lbm_desc* descs, const lbm_rheology* rh, int32_t count, lbm_sizes* out);
+/* Validate (as lbm_create for each, plus the shared-field rules above) and
+ * plan the work list. */
+int lbm_batch_create(const lbm_desc* descs, const lbm_rheology* rh, int32_t count, lbm_batch** out);
+/* Bind caller-owned device buffers and the stream; uploads the parameter
+ * table and work list and sets every simulation to rest. */
+int lbm_batch_bind(lbm_batch* b, void* pdf_dev, void* tau_dev, void* work_dev, void* hip_stream);
+int lbm_batch_init_equilibrium(lbm_batch* b);
+/* Per-simulation population I/O and readout, as the single-domain calls
+ * (writes are allowed at even times only); synchronise. */
+int lbm_batch_write_populations(lbm_batch* b, int32_t sim, const double* host_P, const double* host_tau);
+int lbm_batch_read_populations(lbm_batch* b, int32_t sim, double* host_P, double* host_tau);
+int lbm_batch_read_moments(lbm_batch* b, int32_t sim, double* rho, double* u, double* nu_app, uint8_t* unyielded);
+/* Fused per-simulation monitors every k steps into a device ring of 256
+ * records per simulation; lbm_batch_read_history copies records (each
+ * record = count lbm_monitor, one per simulation) produced since the last
+ * call, at most max_records of them, and synchronises. */
+int lbm_batch_set_monitor_interval(lbm_batch* b, int32_t k);
+int lbm_batch_read_history(lbm_batch* b, lbm_monitor* out, int32_t max_records, int32_t* nrecords);
+/* Monitors of every simulation's current state (count records). */
+int lbm_batch_monitors(lbm_batch* b, lbm_monitor* out);
+/* Steps per captured graph (even; 0 = always launch eagerly; default 100).
+ * A replay starts at times that are multiples of it; other steps are
+ * launched eagerly. */
+int lbm_batch_set_graph_steps(lbm_batch* b, int32_t steps);
+int lbm_batch_step(lbm_batch* b, int64_t nsteps);
+int lbm_batch_time(lbm_batch* b, int64_t* t);
+/* Tile shape chosen for each simulation (3*count ints). */
+int lbm_batch_get_tiles(lbm_batch* b, int32_t* tiles);
+/* Time the tile policies (fewest padded nodes; 64-wide rows; fixed 64x4x1)
+ * on trial_steps steps of the bound batch and keep the fastest; the state
+ * is restored.  Synchronises. */
+int lbm_batch_autotune(lbm_batch* b, int32_t trial_steps);
+int lbm_batch_destroy(lbm_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

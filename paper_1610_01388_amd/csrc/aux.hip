@@ -10,6 +10,8 @@ namespace lbm {
 
 template <int LAT>
 hipError_t launch_step_lattice(int op, int prec, int pat, bool mon, int layout, const StepArgs& a, hipStream_t s);
+template <int LAT>
+hipError_t launch_batch_lattice(int prec, int pat, bool mon, const BatchArgs& a, int grid, hipStream_t s);
 
 // Layout of the stored state (NodeArgs::layout):
 //  0: post-collision, natural slots  (A/B; slot i at x holds P_i(x))
@@ -37,6 +39,7 @@ __device__ __forceinline__ int64_t slot_of(const NodeArgs& a, int x, int y, int 
         return (int64_t)a.wbase[row] + __popcll(word & ((1ull << (x & 63)) - 1ull));
     }
     const int64_t n = x + (int64_t)a.nx * (y + (int64_t)a.ny * z);
+    if (!a.mask) return n;  // no interior solids (batched simulations)
     return a.mask[n] ? -1 : n;
 }
 
@@ -293,6 +296,57 @@ __global__ __launch_bounds__(256) void k_finalize(const double* parts, int64_t n
     }
 }
 
+// Batched monitors: one block per simulation sums its work items' partials
+// in a fixed order into record[(counter mod capacity) * nsims + sim].
+__global__ __launch_bounds__(256) void k_batch_finalize(const double* parts, const BatchSim* sims, int nsims,
+                                                        MonitorRecord* records, const int64_t* counter,
+                                                        int64_t step, int capacity)
+{
+    __shared__ double red[256][MP_COUNT];
+    const int sim = blockIdx.x;
+    const BatchSim& sm = sims[sim];
+    double v[MP_COUNT];
+#pragma unroll
+    for (int k = 0; k < MP_COUNT; ++k) v[k] = 0.0;
+    for (int j = threadIdx.x; j < sm.nitems; j += 256) {
+        const double* p = parts + (int64_t)(sm.item0 + j) * MP_COUNT;
+#pragma unroll
+        for (int k = 0; k < MP_COUNT; ++k) v[k] = (k == MP_UMAX) ? fmax(v[k], p[k]) : v[k] + p[k];
+    }
+#pragma unroll
+    for (int k = 0; k < MP_COUNT; ++k) red[threadIdx.x][k] = v[k];
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+#pragma unroll
+            for (int k = 0; k < MP_COUNT; ++k)
+                red[threadIdx.x][k] = (k == MP_UMAX) ? fmax(red[threadIdx.x][k], red[threadIdx.x + s][k])
+                                                     : red[threadIdx.x][k] + red[threadIdx.x + s][k];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const int64_t c = *counter;
+        MonitorRecord* rec = records + (c % capacity) * nsims + sim;
+        const double ntotal = (double)sm.N;
+        rec->step = c;  // record number; the host maps it to the time step
+        rec->flux[0] = red[0][MP_UX] / ntotal;
+        rec->flux[1] = red[0][MP_UY] / ntotal;
+        rec->flux[2] = red[0][MP_UZ] / ntotal;
+        rec->mass = red[0][MP_MASS];
+        rec->umax = red[0][MP_UMAX];
+        rec->fluid_nodes = (int64_t)red[0][MP_FLUID];
+        rec->unyielded = (int64_t)red[0][MP_UNYIELDED];
+        rec->fallback_nodes = (int64_t)red[0][MP_FALLBACK];
+        rec->nonfinite = (int64_t)red[0][MP_NONFINITE];
+    }
+}
+
+__global__ void k_batch_tick(int64_t* counter)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *counter += 1;
+}
+
 __global__ void k_fill_u8(uint8_t* p, int64_t n, uint8_t v)
 {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -383,6 +437,30 @@ hipError_t launch_fill_u8(uint8_t* p, int64_t n, uint8_t v, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_fill_u8, dim3(nblk(n)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_step(int lat, int prec, int pat, bool mon, const BatchArgs& a, int grid, hipStream_t s)
+{
+    switch (lat) {
+    case 0: return launch_batch_lattice<0>(prec, pat, mon, a, grid, s);
+    case 1: return launch_batch_lattice<1>(prec, pat, mon, a, grid, s);
+    case 2: return launch_batch_lattice<2>(prec, pat, mon, a, grid, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_batch_finalize(const BatchArgs& a, const int* /*unused*/, void* records, const int64_t* counter,
+                                 int64_t step, int capacity, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_batch_finalize, dim3(a.nsims), dim3(256), 0, s, a.partials, a.sims, a.nsims,
+                       (MonitorRecord*)records, counter, step, capacity);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_tick(int64_t* counter, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_batch_tick, dim3(1), dim3(64), 0, s, counter);
     return hipGetLastError();
 }
 

@@ -828,3 +828,571 @@ int lbm_destroy(lbm_domain* dm)
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// batched sweep
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int kBatchHistory = 256;
+
+struct BatchLayout {
+    size_t pdf, tau, sims, work_list, parts, recs, counter, stage, total;
+};
+
+}  // namespace
+
+struct lbm_batch {
+    int count = 0, lat = 0, prec = 0, Q = 0, D = 0;
+    std::vector<lbm_desc> d;
+    std::vector<lbm_rheology> r;
+    std::vector<BatchSim> sims;
+    std::vector<int> work;
+    int nitems = 0;
+    BatchLayout L{};
+    bool bound = false;
+    char* pdf = nullptr;
+    char* tau = nullptr;
+    char* workbuf = nullptr;
+    hipStream_t stream = nullptr;
+    hipStream_t cap = nullptr;
+    int parity = 0;
+    int64_t t = 0;
+    int mon_k = 0;
+    std::vector<int64_t> mon_times;
+    int64_t hist_read = 0;
+    int graph_steps = 100;
+    hipGraphExec_t graph = nullptr;
+    int graph_for_mon = -1;
+    int grid = 0;
+    int policy = 0;  // tile policy: 0 fewest padded nodes (wide rows on ties), 1 prefer 64-wide rows, 2 fixed 64x4x1
+};
+
+namespace {
+
+void tile_for(const lbm_desc& d, int D, int policy, int& tx, int& ty, int& tz)
+{
+    static const int c3[][3] = {{256, 1, 1}, {128, 2, 1}, {64, 4, 1}, {64, 2, 2}, {32, 8, 1},
+                                {32, 4, 2}, {16, 16, 1}, {16, 8, 2}, {16, 4, 4}};
+    static const int c2[][3] = {{256, 1, 1}, {128, 2, 1}, {64, 4, 1}, {32, 8, 1}, {16, 16, 1}, {8, 32, 1}, {4, 64, 1}};
+    const int (*c)[3] = D == 3 ? c3 : c2;
+    const int nc = D == 3 ? 9 : 7;
+    if (policy == 2) { tx = 64; ty = 4; tz = 1; return; }
+    int64_t best = -1;
+    for (int k = 0; k < nc; ++k) {
+        if (policy == 1 && c[k][0] < 64) continue;
+        const int64_t pad = (int64_t)((d.nx + c[k][0] - 1) / c[k][0]) * c[k][0] * (int64_t)((d.ny + c[k][1] - 1) / c[k][1]) *
+                            c[k][1] * (int64_t)((d.nz + c[k][2] - 1) / c[k][2]) * c[k][2];
+        if (best < 0 || pad < best) { best = pad; tx = c[k][0]; ty = c[k][1]; tz = c[k][2]; }
+    }
+}
+
+int batch_plan(lbm_batch* b)
+{
+    b->sims.assign(b->count, BatchSim{});
+    b->work.clear();
+    int64_t off_pdf = 0, off_tau = 0;
+    for (int k = 0; k < b->count; ++k) {
+        BatchSim& s = b->sims[k];
+        const lbm_desc& d = b->d[k];
+        s.nx = d.nx; s.ny = d.ny; s.nz = d.nz;
+        for (int a = 0; a < 3; ++a) s.per[a] = d.periodic[a] ? 1 : 0;
+        if (b->D == 2) s.per[2] = 1;
+        s.op = b->r[k].op;
+        tile_for(d, b->D, b->policy, s.tx, s.ty, s.tz);
+        s.ntx = (d.nx + s.tx - 1) / s.tx;
+        s.nty = (d.ny + s.ty - 1) / s.ty;
+        s.ntz = (d.nz + s.tz - 1) / s.tz;
+        const int64_t items = (int64_t)s.ntx * s.nty * s.ntz;
+        if ((int64_t)b->work.size() + items > INT32_MAX) return fail(LBM_EINVAL, "batch too large");
+        s.item0 = (int)b->work.size();
+        s.nitems = (int)items;
+        for (int64_t j = 0; j < items; ++j) b->work.push_back(k);
+        s.N = (int64_t)d.nx * d.ny * d.nz;
+        s.off_pdf = off_pdf;
+        s.off_tau = off_tau;
+        off_pdf += (s.N * b->Q + 63) / 64 * 64;
+        off_tau += (s.N + 63) / 64 * 64;
+        s.cd = make_coll<double>(b->r[k]);
+        s.cf = make_coll<float>(b->r[k]);
+    }
+    b->nitems = (int)b->work.size();
+    BatchLayout& L = b->L;
+    L.pdf = align_up((size_t)off_pdf * prec_bytes(b->prec));
+    bool any_pr = false;
+    for (auto& r : b->r) any_pr |= r.op == LBM_PR;
+    L.tau = any_pr ? align_up((size_t)off_tau * (b->prec == LBM_FP64 ? 8 : 4)) : 0;
+    L.sims = 0;
+    L.work_list = align_up(sizeof(BatchSim) * b->count);
+    L.parts = L.work_list + align_up(sizeof(int) * b->nitems);
+    L.recs = L.parts + align_up((size_t)b->nitems * MP_COUNT * sizeof(double));
+    L.counter = L.recs + align_up((size_t)kBatchHistory * b->count * sizeof(MonitorRecord));
+    L.stage = L.counter + kAlign;
+    int64_t maxN = 0;
+    for (auto& s : b->sims) maxN = std::max(maxN, s.N);
+    size_t stage = std::min(kStageMax, align_up((size_t)maxN * (b->Q + 1) * 8));
+    stage = std::max(stage, align_up((size_t)(b->Q + 1) * 8 * 256));
+    L.total = L.stage + stage;
+    return LBM_OK;
+}
+
+int batch_need(lbm_batch* b)
+{
+    if (!b) return fail(LBM_EINVAL, "batch is NULL");
+    if (!b->bound) return fail(LBM_ESTATE, "batch has no bound buffers (call lbm_batch_bind)");
+    return LBM_OK;
+}
+
+BatchArgs batch_args(lbm_batch* b)
+{
+    BatchArgs a{};
+    a.sims = (const BatchSim*)(b->workbuf + b->L.sims);
+    a.work = (const int*)(b->workbuf + b->L.work_list);
+    a.nitems = b->nitems;
+    a.nsims = b->count;
+    a.pdf = b->pdf;
+    a.tau = b->tau;
+    a.partials = (double*)(b->workbuf + b->L.parts);
+    a.h16_scale = std::ldexp(1.0f, -b->r[0].fp16_scale_log2);
+    a.h16_inv = std::ldexp(1.0f, b->r[0].fp16_scale_log2);
+    a.fallback = (b->prec != LBM_FP64 && b->r[0].fp64_fallback) ? 1 : 0;
+    return a;
+}
+
+// Enqueue nsteps steps on stream s (eagerly or while s is being captured).
+int batch_enqueue(lbm_batch* b, int64_t nsteps, hipStream_t s, int& parity, int64_t& t, bool record_times)
+{
+    BatchArgs a = batch_args(b);
+    for (int64_t k = 0; k < nsteps; ++k) {
+        const int pat = parity == 0 ? PAT_AA_PULL : PAT_AA_LOCAL;
+        const bool mon = b->mon_k > 0 && (t % b->mon_k) == 0;
+        HIPCHK(launch_batch_step(b->lat, b->prec, pat, mon, a, b->grid, s));
+        if (mon) {
+            HIPCHK(launch_batch_finalize(a, nullptr, b->workbuf + b->L.recs, (const int64_t*)(b->workbuf + b->L.counter),
+                                         t, kBatchHistory, s));
+            HIPCHK(launch_batch_tick((int64_t*)(b->workbuf + b->L.counter), s));
+            if (record_times) b->mon_times.push_back(t);
+        }
+        parity ^= 1;
+        ++t;
+    }
+    return LBM_OK;
+}
+
+void batch_drop_graph(lbm_batch* b)
+{
+    if (b->graph) (void)hipGraphExecDestroy(b->graph);
+    b->graph = nullptr;
+    b->graph_for_mon = -1;
+}
+
+// Capture graph_steps steps starting at parity 0 and a time that is a
+// multiple of graph_steps (so monitor steps fall at the same offsets).
+int batch_build_graph(lbm_batch* b)
+{
+    batch_drop_graph(b);
+    if (!b->cap) HIPCHK(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+    HIPCHK(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+    int parity = 0;
+    int64_t t = 0;
+    int rc = batch_enqueue(b, b->graph_steps, b->cap, parity, t, false);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(b->cap, &g);
+    if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(LBM_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    const hipError_t e2 = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e2 != hipSuccess) {
+        b->graph = nullptr;
+        return fail(LBM_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e2));
+    }
+    b->graph_for_mon = b->mon_k;
+    return LBM_OK;
+}
+
+NodeArgs batch_node_args(lbm_batch* b, int k)
+{
+    const BatchSim& s = b->sims[k];
+    NodeArgs a{};
+    a.pdf = b->pdf + (size_t)s.off_pdf * prec_bytes(b->prec);
+    a.tau = b->tau ? (void*)(b->tau + (size_t)s.off_tau * (b->prec == LBM_FP64 ? 8 : 4)) : nullptr;
+    if (b->r[k].op != LBM_PR) a.tau = nullptr;
+    a.mask = nullptr;
+    a.partials = (double*)(b->workbuf + b->L.parts);
+    a.N = s.N;
+    a.S = s.N;
+    a.nx = s.nx; a.ny = s.ny; a.nz = s.nz;
+    for (int q = 0; q < 3; ++q) a.per[q] = s.per[q];
+    a.layout = b->parity == 0 ? 1 : 2;
+    a.compact = 0;
+    a.h16_scale = std::ldexp(1.0f, -b->r[k].fp16_scale_log2);
+    a.h16_inv = std::ldexp(1.0f, b->r[k].fp16_scale_log2);
+    a.cd = make_coll<double>(b->r[k]);
+    a.cf = make_coll<float>(b->r[k]);
+    return a;
+}
+
+int batch_check_sim(lbm_batch* b, int32_t sim)
+{
+    int rc = batch_need(b);
+    if (rc) return rc;
+    if (sim < 0 || sim >= b->count) return fail(LBM_EINVAL, "simulation index %d outside 0..%d", sim, b->count - 1);
+    return LBM_OK;
+}
+
+int batch_validate(const lbm_desc* descs, const lbm_rheology* rh, int32_t count)
+{
+    if (!descs || !rh || count < 1) return fail(LBM_EINVAL, "need count >= 1 descriptors and rheologies");
+    for (int k = 0; k < count; ++k) {
+        int rc = check_desc(&descs[k]);
+        if (rc) return fail(rc, "simulation %d: %s", k, g_err.c_str());
+        if ((rc = check_rheology(&rh[k]))) return fail(rc, "simulation %d: %s", k, g_err.c_str());
+        if (descs[k].lattice != descs[0].lattice || descs[k].precision != descs[0].precision)
+            return fail(LBM_EINVAL, "all simulations of a batch share one lattice and one precision");
+        if (descs[k].scheme != LBM_AA) return fail(LBM_EINVAL, "batches use the AA scheme");
+        if (rh[k].fp64_fallback != rh[0].fp64_fallback || rh[k].fp16_scale_log2 != rh[0].fp16_scale_log2)
+            return fail(LBM_EINVAL, "all simulations of a batch share the fallback flag and the FP16 scale");
+    }
+    return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_batch_query_sizes(const lbm_desc* descs, const lbm_rheology* rh, int32_t count, lbm_sizes* out)
+{
+    int rc = batch_validate(descs, rh, count);
+    if (rc) return rc;
+    if (!out) return fail(LBM_EINVAL, "out is NULL");
+    lbm_batch tmp;
+    tmp.count = count;
+    tmp.lat = descs[0].lattice;
+    tmp.prec = descs[0].precision;
+    tmp.Q = lattice_q(tmp.lat);
+    tmp.D = lattice_d(tmp.lat);
+    tmp.d.assign(descs, descs + count);
+    tmp.r.assign(rh, rh + count);
+    if ((rc = batch_plan(&tmp))) return rc;
+    out->pdf_bytes = tmp.L.pdf;
+    out->tau_bytes = tmp.L.tau;
+    out->mask_bytes = 0;
+    out->work_bytes = tmp.L.total;
+    return LBM_OK;
+}
+
+int lbm_batch_create(const lbm_desc* descs, const lbm_rheology* rh, int32_t count, lbm_batch** out)
+{
+    int rc = batch_validate(descs, rh, count);
+    if (rc) return rc;
+    if (!out) return fail(LBM_EINVAL, "out is NULL");
+    lbm_batch* b = new (std::nothrow) lbm_batch();
+    if (!b) return fail(LBM_EINVAL, "host allocation failed");
+    b->count = count;
+    b->lat = descs[0].lattice;
+    b->prec = descs[0].precision;
+    b->Q = lattice_q(b->lat);
+    b->D = lattice_d(b->lat);
+    b->d.assign(descs, descs + count);
+    b->r.assign(rh, rh + count);
+    if ((rc = batch_plan(b))) {
+        delete b;
+        return rc;
+    }
+    *out = b;
+    return LBM_OK;
+}
+
+int lbm_batch_bind(lbm_batch* b, void* pdf_dev, void* tau_dev, void* work_dev, void* hip_stream)
+{
+    if (!b) return fail(LBM_EINVAL, "batch is NULL");
+    if (!pdf_dev || !work_dev || (b->L.tau && !tau_dev)) return fail(LBM_EINVAL, "missing device buffer");
+    if (((uintptr_t)pdf_dev | (uintptr_t)work_dev | (uintptr_t)(tau_dev ? tau_dev : pdf_dev)) % 16)
+        return fail(LBM_EINVAL, "device buffers must be 16-byte aligned");
+    b->pdf = (char*)pdf_dev;
+    b->tau = (char*)tau_dev;
+    b->workbuf = (char*)work_dev;
+    b->stream = (hipStream_t)hip_stream;
+    b->bound = true;
+    b->grid = std::max(1, std::min(b->nitems, 4096));
+    batch_drop_graph(b);
+    HIPCHK(hipMemcpyAsync(b->workbuf + b->L.sims, b->sims.data(), sizeof(BatchSim) * b->count, hipMemcpyHostToDevice,
+                          b->stream));
+    HIPCHK(hipMemcpyAsync(b->workbuf + b->L.work_list, b->work.data(), sizeof(int) * b->nitems, hipMemcpyHostToDevice,
+                          b->stream));
+    HIPCHK(hipStreamSynchronize(b->stream));
+    return lbm_batch_init_equilibrium(b);
+}
+
+int lbm_batch_init_equilibrium(lbm_batch* b)
+{
+    int rc = batch_need(b);
+    if (rc) return rc;
+    b->parity = 0;
+    b->t = 0;
+    b->mon_times.clear();
+    b->hist_read = 0;
+    HIPCHK(hipMemsetAsync(b->workbuf + b->L.counter, 0, sizeof(int64_t), b->stream));
+    for (int k = 0; k < b->count; ++k) {
+        NodeArgs a = batch_node_args(b, k);
+        HIPCHK(launch_init(b->lat, b->r[k].op, b->prec, a, b->r[k].rho0, b->stream));
+    }
+    HIPCHK(hipStreamSynchronize(b->stream));
+    return LBM_OK;
+}
+
+int lbm_batch_write_populations(lbm_batch* b, int32_t sim, const double* host_P, const double* host_tau)
+{
+    int rc = batch_check_sim(b, sim);
+    if (rc) return rc;
+    if (!host_P) return fail(LBM_EINVAL, "host_P is NULL");
+    if (b->parity != 0) return fail(LBM_ESTATE, "write populations only between step pairs (even time)");
+    const BatchSim& s = b->sims[sim];
+    const int Q = b->Q;
+    const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(s.N, (int64_t)((b->L.total - b->L.stage) / ((Q + 1) * 8))));
+    double* stage = (double*)(b->workbuf + b->L.stage);
+    for (int64_t n0 = 0; n0 < s.N; n0 += chunk) {
+        const int64_t cnt = std::min(chunk, s.N - n0);
+        HIPCHK(hipMemcpy2DAsync(stage, cnt * 8, host_P + n0, s.N * 8, cnt * 8, Q, hipMemcpyHostToDevice, b->stream));
+        NodeArgs a = batch_node_args(b, sim);
+        if (!(host_tau && a.tau)) a.tau = nullptr;
+        else HIPCHK(hipMemcpyAsync(stage + (size_t)Q * cnt, host_tau + n0, cnt * 8, hipMemcpyHostToDevice, b->stream));
+        a.out = stage;
+        a.n0 = n0;
+        a.count = cnt;
+        HIPCHK(launch_pop_write(b->lat, b->prec, a, b->stream));
+        HIPCHK(hipStreamSynchronize(b->stream));
+    }
+    return LBM_OK;
+}
+
+int lbm_batch_read_populations(lbm_batch* b, int32_t sim, double* host_P, double* host_tau)
+{
+    int rc = batch_check_sim(b, sim);
+    if (rc) return rc;
+    if (!host_P) return fail(LBM_EINVAL, "host_P is NULL");
+    const BatchSim& s = b->sims[sim];
+    const int Q = b->Q;
+    const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(s.N, (int64_t)((b->L.total - b->L.stage) / ((Q + 1) * 8))));
+    double* stage = (double*)(b->workbuf + b->L.stage);
+    for (int64_t n0 = 0; n0 < s.N; n0 += chunk) {
+        const int64_t cnt = std::min(chunk, s.N - n0);
+        NodeArgs a = batch_node_args(b, sim);
+        if (!host_tau) a.tau = nullptr;
+        a.out = stage;
+        a.n0 = n0;
+        a.count = cnt;
+        HIPCHK(launch_pop_read(b->lat, b->prec, a, b->stream));
+        HIPCHK(hipMemcpy2DAsync(host_P + n0, s.N * 8, stage, cnt * 8, cnt * 8, Q, hipMemcpyDeviceToHost, b->stream));
+        if (a.tau)
+            HIPCHK(hipMemcpyAsync(host_tau + n0, stage + (size_t)Q * cnt, cnt * 8, hipMemcpyDeviceToHost, b->stream));
+        HIPCHK(hipStreamSynchronize(b->stream));
+    }
+    return LBM_OK;
+}
+
+int lbm_batch_read_moments(lbm_batch* b, int32_t sim, double* rho, double* u, double* nu_app, uint8_t* unyielded)
+{
+    int rc = batch_check_sim(b, sim);
+    if (rc) return rc;
+    const BatchSim& s = b->sims[sim];
+    const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(s.N, (int64_t)((b->L.total - b->L.stage) / 41)));
+    double* stage = (double*)(b->workbuf + b->L.stage);
+    for (int64_t n0 = 0; n0 < s.N; n0 += chunk) {
+        const int64_t cnt = std::min(chunk, s.N - n0);
+        NodeArgs a = batch_node_args(b, sim);
+        a.out = stage;
+        a.out_flags = (uint8_t*)(stage + 5 * cnt);
+        a.n0 = n0;
+        a.count = cnt;
+        HIPCHK(launch_readout(b->lat, b->r[sim].op, b->prec, a, b->stream, nullptr));
+        if (rho) HIPCHK(hipMemcpyAsync(rho + n0, stage, cnt * 8, hipMemcpyDeviceToHost, b->stream));
+        if (u)
+            for (int k = 0; k < 3; ++k)
+                HIPCHK(hipMemcpyAsync(u + (size_t)k * s.N + n0, stage + (size_t)(1 + k) * cnt, cnt * 8,
+                                      hipMemcpyDeviceToHost, b->stream));
+        if (nu_app) HIPCHK(hipMemcpyAsync(nu_app + n0, stage + 4 * cnt, cnt * 8, hipMemcpyDeviceToHost, b->stream));
+        if (unyielded) HIPCHK(hipMemcpyAsync(unyielded + n0, a.out_flags, cnt, hipMemcpyDeviceToHost, b->stream));
+        HIPCHK(hipStreamSynchronize(b->stream));
+    }
+    return LBM_OK;
+}
+
+int lbm_batch_set_monitor_interval(lbm_batch* b, int32_t k)
+{
+    if (!b) return fail(LBM_EINVAL, "batch is NULL");
+    if (k < 0) return fail(LBM_EINVAL, "interval must be >= 0");
+    b->mon_k = k;
+    return LBM_OK;
+}
+
+int lbm_batch_set_graph_steps(lbm_batch* b, int32_t steps)
+{
+    if (!b) return fail(LBM_EINVAL, "batch is NULL");
+    if (steps < 0 || (steps % 2)) return fail(LBM_EINVAL, "graph steps must be even and >= 0 (0 = no graph)");
+    b->graph_steps = steps;
+    batch_drop_graph(b);
+    return LBM_OK;
+}
+
+int lbm_batch_step(lbm_batch* b, int64_t nsteps)
+{
+    int rc = batch_need(b);
+    if (rc) return rc;
+    if (nsteps < 0) return fail(LBM_EINVAL, "nsteps must be >= 0");
+    const int G = b->graph_steps;
+    while (nsteps > 0) {
+        const bool graph_ok = G > 0 && nsteps >= G && b->parity == 0 && (b->t % G) == 0 &&
+                              (b->mon_k == 0 || (G % b->mon_k) == 0);
+        if (!graph_ok) {
+            // eager steps up to the next point where a replay can start
+            int64_t n = 1;
+            if (G > 0 && (b->t % G) != 0) n = std::min<int64_t>(nsteps, G - b->t % G);
+            else if (G == 0 || nsteps < G || (b->mon_k && G % b->mon_k)) n = nsteps;
+            if ((rc = batch_enqueue(b, n, b->stream, b->parity, b->t, true))) return rc;
+            nsteps -= n;
+            continue;
+        }
+        if (!b->graph || b->graph_for_mon != b->mon_k)
+            if ((rc = batch_build_graph(b))) return rc;
+        HIPCHK(hipGraphLaunch(b->graph, b->stream));
+        if (b->mon_k > 0)
+            for (int64_t k = 0; k < G; k += b->mon_k) b->mon_times.push_back(b->t + k);
+        b->t += G;
+        nsteps -= G;
+    }
+    return LBM_OK;
+}
+
+int lbm_batch_time(lbm_batch* b, int64_t* t)
+{
+    if (!b || !t) return fail(LBM_EINVAL, "NULL argument");
+    *t = b->t;
+    return LBM_OK;
+}
+
+int lbm_batch_read_history(lbm_batch* b, lbm_monitor* out, int32_t max_records, int32_t* nrecords)
+{
+    int rc = batch_need(b);
+    if (rc) return rc;
+    if (!nrecords || (max_records > 0 && !out)) return fail(LBM_EINVAL, "NULL argument");
+    HIPCHK(hipStreamSynchronize(b->stream));
+    const int64_t written = (int64_t)b->mon_times.size();
+    b->hist_read = std::max(b->hist_read, written - kBatchHistory);
+    const int64_t n = std::min<int64_t>(written - b->hist_read, max_records);
+    const MonitorRecord* ring = (const MonitorRecord*)(b->workbuf + b->L.recs);
+    for (int64_t j = 0; j < n; ++j) {
+        const int64_t c = b->hist_read + j;
+        HIPCHK(hipMemcpy(out + j * b->count, ring + (c % kBatchHistory) * b->count, sizeof(MonitorRecord) * b->count,
+                         hipMemcpyDeviceToHost));
+        for (int k = 0; k < b->count; ++k) out[j * b->count + k].step = b->mon_times[c];
+    }
+    b->hist_read += n;
+    *nrecords = (int32_t)n;
+    return LBM_OK;
+}
+
+int lbm_batch_monitors(lbm_batch* b, lbm_monitor* out)
+{
+    int rc = batch_need(b);
+    if (rc) return rc;
+    if (!out) return fail(LBM_EINVAL, "out is NULL");
+    for (int k = 0; k < b->count; ++k) {
+        NodeArgs a = batch_node_args(b, k);
+        a.n0 = 0;
+        a.count = b->sims[k].N;
+        a.reduce = 1;
+        int64_t nb = 0;
+        HIPCHK(launch_readout(b->lat, b->r[k].op, b->prec, a, b->stream, &nb));
+        // the on-demand record lives after the history ring's counter
+        char* rec = b->workbuf + b->L.counter + 64;
+        HIPCHK(launch_finalize(a.partials, nb, rec, b->t, (double)b->sims[k].N, b->stream));
+        HIPCHK(hipMemcpyAsync(out + k, rec, sizeof(MonitorRecord), hipMemcpyDeviceToHost, b->stream));
+        HIPCHK(hipStreamSynchronize(b->stream));
+    }
+    return LBM_OK;
+}
+
+int lbm_batch_get_tiles(lbm_batch* b, int32_t* tiles)
+{
+    if (!b || !tiles) return fail(LBM_EINVAL, "NULL argument");
+    for (int k = 0; k < b->count; ++k) {
+        tiles[3 * k] = b->sims[k].tx;
+        tiles[3 * k + 1] = b->sims[k].ty;
+        tiles[3 * k + 2] = b->sims[k].tz;
+    }
+    return LBM_OK;
+}
+
+int lbm_batch_autotune(lbm_batch* b, int32_t trial_steps)
+{
+    int rc = batch_need(b);
+    if (rc) return rc;
+    if (trial_steps < 2 || (trial_steps % 2)) return fail(LBM_EINVAL, "trial_steps must be even and >= 2");
+    HIPCHK(hipStreamSynchronize(b->stream));
+    // save the state (populations and relaxation times); trial steps run on it
+    std::vector<char> pdf(b->L.pdf), tau(b->L.tau);
+    HIPCHK(hipMemcpy(pdf.data(), b->pdf, b->L.pdf, hipMemcpyDeviceToHost));
+    if (b->L.tau) HIPCHK(hipMemcpy(tau.data(), b->tau, b->L.tau, hipMemcpyDeviceToHost));
+    const int parity = b->parity, mon_k = b->mon_k, keep = b->policy;
+    const int64_t t = b->t;
+    const auto times = b->mon_times;
+    b->mon_k = 0;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    int best = keep;
+    float best_ms = 1e30f;
+    for (int pol = 0; pol < 3 && rc == LBM_OK; ++pol) {
+        b->policy = pol;
+        if ((rc = batch_plan(b))) break;
+        HIPCHK(hipMemcpy(b->workbuf + b->L.sims, b->sims.data(), sizeof(BatchSim) * b->count, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(b->workbuf + b->L.work_list, b->work.data(), sizeof(int) * b->nitems, hipMemcpyHostToDevice));
+        b->grid = std::max(1, std::min(b->nitems, 4096));
+        int par = b->parity;
+        int64_t tt = b->t;
+        if ((rc = batch_enqueue(b, 2, b->stream, par, tt, false))) break;
+        HIPCHK(hipEventRecord(e0, b->stream));
+        if ((rc = batch_enqueue(b, trial_steps, b->stream, par, tt, false))) break;
+        HIPCHK(hipEventRecord(e1, b->stream));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = pol;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    b->policy = best;
+    int rc2 = batch_plan(b);
+    if (rc2 == LBM_OK) {
+        HIPCHK(hipMemcpy(b->workbuf + b->L.sims, b->sims.data(), sizeof(BatchSim) * b->count, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(b->workbuf + b->L.work_list, b->work.data(), sizeof(int) * b->nitems, hipMemcpyHostToDevice));
+        b->grid = std::max(1, std::min(b->nitems, 4096));
+    }
+    HIPCHK(hipMemcpy(b->pdf, pdf.data(), b->L.pdf, hipMemcpyHostToDevice));
+    if (b->L.tau) HIPCHK(hipMemcpy(b->tau, tau.data(), b->L.tau, hipMemcpyHostToDevice));
+    b->parity = parity;
+    b->t = t;
+    b->mon_k = mon_k;
+    b->mon_times = times;
+    batch_drop_graph(b);
+    return rc ? rc : rc2;
+}
+
+int lbm_batch_destroy(lbm_batch* b)
+{
+    if (!b) return LBM_OK;
+    if (b->bound && b->stream) (void)hipStreamSynchronize(b->stream);
+    batch_drop_graph(b);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    delete b;
+    return LBM_OK;
+}
+
+}  // extern "C"

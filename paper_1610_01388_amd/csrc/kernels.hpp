@@ -86,7 +86,40 @@ struct NodeArgs {
     Coll<float> cf;
 };
 
+// Batched sweep: many independent all-fluid domains (walls only through
+// non-periodic axes) stepped together.  Each simulation is cut into tiles of
+// 256 nodes; one work item = one tile; a persistent grid walks the work list.
+struct BatchSim {
+    int nx, ny, nz;
+    int per[3];
+    int op;
+    int tx, ty, tz;        // tile shape (tx*ty*tz == 256)
+    int ntx, nty, ntz;
+    int item0, nitems;     // this simulation's work items [item0, item0 + nitems)
+    int pad_;
+    int64_t N;             // nodes
+    int64_t off_pdf;       // element offset of the simulation's population block ([i][n], stride N)
+    int64_t off_tau;       // element offset of its relaxation-time block (PR)
+    Coll<double> cd;
+    Coll<float> cf;
+};
+
+struct BatchArgs {
+    const BatchSim* sims;
+    const int* work;       // work item -> simulation index
+    int nitems, nsims;
+    void* pdf;             // arena (AA: one copy)
+    void* tau;
+    double* partials;      // MON: MP_COUNT per work item
+    float h16_scale, h16_inv;
+    int fallback;
+};
+
 hipError_t launch_step(int lat, int op, int prec, int pat, bool mon, int layout, const StepArgs& a, hipStream_t s);
+hipError_t launch_batch_step(int lat, int prec, int pat, bool mon, const BatchArgs& a, int grid, hipStream_t s);
+hipError_t launch_batch_finalize(const BatchArgs& a, const int* sims_item0, void* records, const int64_t* counter,
+                                 int64_t step, int capacity, hipStream_t s);
+hipError_t launch_batch_tick(int64_t* counter, hipStream_t s);
 hipError_t launch_finalize(const double* partials, int64_t nparts, void* record, int64_t step, double ntotal,
                            hipStream_t s);
 hipError_t launch_init(int lat, int op, int prec, const NodeArgs& a, double rho0, hipStream_t s);

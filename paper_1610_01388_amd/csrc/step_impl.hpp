@@ -20,23 +20,23 @@ namespace lbm {
 // the FP64 redo of near-yield nodes in reduced precision.
 template <int LAT, int OP, int PREC>
 __device__ __forceinline__ void collide_node(typename Store<PREC>::C (&h)[Lattice<LAT>::Q],
-                                             typename Store<PREC>::C tau_prev, const StepArgs& a,
+                                             typename Store<PREC>::C tau_prev, int fallback,
+                                             const Coll<double>& cd, const Coll<typename Store<PREC>::C>& cp,
                                              Moments<typename Store<PREC>::C>& mo,
                                              Pre<typename Store<PREC>::C>& pr, bool& used_fb)
 {
     using C = typename Store<PREC>::C;
     constexpr int Q = Lattice<LAT>::Q;
-    const Coll<C>& cp = coll_of<C>(a);
     mo = moments<LAT>(h);
     pr = rheology<LAT, OP>(mo, cp, tau_prev);
     if constexpr (PREC != PREC_F64) {
-        if (a.fallback && pr.near_yield) {
+        if (fallback && pr.near_yield) {
             double hd[Q];
 #pragma unroll
             for (int i = 0; i < Q; ++i) hd[i] = (double)h[i];
             const Moments<double> md = moments<LAT>(hd);
-            const Pre<double> pd = rheology<LAT, OP>(md, a.cd, (double)tau_prev);
-            relax<LAT, OP>(hd, md, pd, a.cd);
+            const Pre<double> pd = rheology<LAT, OP>(md, cd, (double)tau_prev);
+            relax<LAT, OP>(hd, md, pd, cd);
 #pragma unroll
             for (int i = 0; i < Q; ++i) h[i] = (C)hd[i];
             pr.tau_p = (C)pd.tau_p;
@@ -164,7 +164,7 @@ __global__ __launch_bounds__(256) void k_step(const StepArgs a)
         }
         if constexpr (OP == OP_PR) tau_prev = (C)((const T*)a.tau)[n];
 
-        collide_node<LAT, OP, PREC>(h, tau_prev, a, mo, pr, used_fb);
+        collide_node<LAT, OP, PREC>(h, tau_prev, a.fallback, a.cd, cp, mo, pr, used_fb);
 
         S* B = (S*)a.dst;
 #pragma unroll
@@ -324,7 +324,7 @@ __global__ __launch_bounds__(256) void k_step_compact(const StepArgs a, const ui
         }
         if constexpr (OP == OP_PR) tau_prev = (C)((const T*)a.tau)[k];
 
-        collide_node<LAT, OP, PREC>(h, tau_prev, a, mo, pr, used_fb);
+        collide_node<LAT, OP, PREC>(h, tau_prev, a.fallback, a.cd, cp, mo, pr, used_fb);
 
         S* B = (S*)a.dst;
 #pragma unroll

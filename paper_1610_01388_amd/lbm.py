@@ -67,7 +67,12 @@ EXPORTS = ["lbm_last_error", "lbm_lattice_info", "lbm_query_sizes", "lbm_create"
            "lbm_set_mask", "lbm_init_equilibrium", "lbm_write_populations", "lbm_read_populations",
            "lbm_step", "lbm_time", "lbm_set_monitor_interval", "lbm_read_history", "lbm_monitors",
            "lbm_set_umax_limit", "lbm_read_moments", "lbm_save", "lbm_load", "lbm_set_tile",
-           "lbm_get_tile", "lbm_autotune", "lbm_destroy"]
+           "lbm_get_tile", "lbm_autotune", "lbm_destroy",
+           "lbm_batch_query_sizes", "lbm_batch_create", "lbm_batch_bind", "lbm_batch_init_equilibrium",
+           "lbm_batch_write_populations", "lbm_batch_read_populations", "lbm_batch_read_moments",
+           "lbm_batch_set_monitor_interval", "lbm_batch_read_history", "lbm_batch_monitors",
+           "lbm_batch_set_graph_steps", "lbm_batch_step", "lbm_batch_time", "lbm_batch_get_tiles",
+           "lbm_batch_autotune", "lbm_batch_destroy"]
 
 _lib = None
 
@@ -114,6 +119,24 @@ def load_library(path: str = LIB_PATH):
         "lbm_get_tile": ([vp, i32p, i32p, i32p], ctypes.c_int),
         "lbm_autotune": ([vp, i32], ctypes.c_int),
         "lbm_destroy": ([vp], ctypes.c_int),
+        "lbm_batch_query_sizes": ([ctypes.POINTER(lbm_desc), ctypes.POINTER(lbm_rheology), i32,
+                                   ctypes.POINTER(lbm_sizes)], ctypes.c_int),
+        "lbm_batch_create": ([ctypes.POINTER(lbm_desc), ctypes.POINTER(lbm_rheology), i32,
+                              ctypes.POINTER(vp)], ctypes.c_int),
+        "lbm_batch_bind": ([vp, vp, vp, vp, vp], ctypes.c_int),
+        "lbm_batch_init_equilibrium": ([vp], ctypes.c_int),
+        "lbm_batch_write_populations": ([vp, i32, dp, dp], ctypes.c_int),
+        "lbm_batch_read_populations": ([vp, i32, dp, dp], ctypes.c_int),
+        "lbm_batch_read_moments": ([vp, i32, dp, dp, dp, u8p], ctypes.c_int),
+        "lbm_batch_set_monitor_interval": ([vp, i32], ctypes.c_int),
+        "lbm_batch_read_history": ([vp, ctypes.POINTER(lbm_monitor), i32, i32p], ctypes.c_int),
+        "lbm_batch_monitors": ([vp, ctypes.POINTER(lbm_monitor)], ctypes.c_int),
+        "lbm_batch_set_graph_steps": ([vp, i32], ctypes.c_int),
+        "lbm_batch_step": ([vp, i64], ctypes.c_int),
+        "lbm_batch_time": ([vp, ctypes.POINTER(i64)], ctypes.c_int),
+        "lbm_batch_get_tiles": ([vp, i32p], ctypes.c_int),
+        "lbm_batch_autotune": ([vp, i32], ctypes.c_int),
+        "lbm_batch_destroy": ([vp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -381,3 +404,176 @@ class Domain:
 
     def synchronize(self):
         self.stream.synchronize()
+
+
+# --- batched sweep ------------------------------------------------------------
+
+def _arrays(descs, rhs):
+    n = len(descs)
+    D = (lbm_desc * n)(*descs)
+    R = (lbm_rheology * n)(*rhs)
+    return D, R
+
+
+def lbm_batch_query_sizes(descs, rhs):
+    D, R = _arrays(descs, rhs)
+    s = lbm_sizes()
+    _check(load_library().lbm_batch_query_sizes(D, R, len(descs), ctypes.byref(s)))
+    return s
+
+
+def lbm_batch_create(descs, rhs):
+    D, R = _arrays(descs, rhs)
+    h = ctypes.c_void_p()
+    _check(load_library().lbm_batch_create(D, R, len(descs), ctypes.byref(h)))
+    return h
+
+
+def lbm_batch_bind(h, pdf, tau, work, stream):
+    _check(load_library().lbm_batch_bind(h, pdf, tau, work, stream))
+
+
+def lbm_batch_init_equilibrium(h):
+    _check(load_library().lbm_batch_init_equilibrium(h))
+
+
+def lbm_batch_write_populations(h, sim, P, tau=None):
+    P = np.ascontiguousarray(P, dtype=np.float64)
+    t = None if tau is None else np.ascontiguousarray(tau, dtype=np.float64)
+    _check(load_library().lbm_batch_write_populations(h, int(sim), _dp(P), _dp(t)))
+
+
+def lbm_batch_read_populations(h, sim, q, N, with_tau=False):
+    P = np.zeros((q, N))
+    t = np.zeros(N) if with_tau else None
+    _check(load_library().lbm_batch_read_populations(h, int(sim), _dp(P), _dp(t)))
+    return P, t
+
+
+def lbm_batch_read_moments(h, sim, N):
+    rho, u, nu = np.zeros(N), np.zeros((3, N)), np.zeros(N)
+    uy = np.zeros(N, dtype=np.uint8)
+    _check(load_library().lbm_batch_read_moments(h, int(sim), _dp(rho), _dp(u), _dp(nu),
+                                                 uy.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))))
+    return rho, u, nu, uy
+
+
+def lbm_batch_set_monitor_interval(h, k):
+    _check(load_library().lbm_batch_set_monitor_interval(h, int(k)))
+
+
+def lbm_batch_read_history(h, count, max_records=256):
+    buf = (lbm_monitor * (max_records * count))()
+    n = ctypes.c_int32()
+    _check(load_library().lbm_batch_read_history(h, buf, max_records, ctypes.byref(n)))
+    return [[buf[r * count + k].as_dict() for k in range(count)] for r in range(n.value)]
+
+
+def lbm_batch_monitors(h, count):
+    buf = (lbm_monitor * count)()
+    _check(load_library().lbm_batch_monitors(h, buf))
+    return [buf[k].as_dict() for k in range(count)]
+
+
+def lbm_batch_set_graph_steps(h, steps):
+    _check(load_library().lbm_batch_set_graph_steps(h, int(steps)))
+
+
+def lbm_batch_step(h, n):
+    _check(load_library().lbm_batch_step(h, int(n)))
+
+
+def lbm_batch_time(h):
+    t = ctypes.c_int64()
+    _check(load_library().lbm_batch_time(h, ctypes.byref(t)))
+    return t.value
+
+
+def lbm_batch_get_tiles(h, count):
+    t = np.zeros(3 * count, dtype=np.int32)
+    _check(load_library().lbm_batch_get_tiles(h, t.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+    return t.reshape(count, 3)
+
+
+def lbm_batch_autotune(h, trial_steps=10):
+    _check(load_library().lbm_batch_autotune(h, int(trial_steps)))
+
+
+def lbm_batch_destroy(h):
+    _check(load_library().lbm_batch_destroy(h))
+
+
+class Batch:
+    """Owns one lbm_batch and its torch-allocated device buffers.  cases:
+    dicts with lattice, dims, periodic, op, nu_p, sigma_y, m, g (the
+    inputs.batch_sweep recipe)."""
+
+    def __init__(self, cases, precision="FP32", device=None, stream=None, **rh_kw):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("liblbm needs a HIP GPU; none is visible")
+        load_library()
+        self.torch = torch
+        self.cases = cases
+        self.descs = [make_desc(c["lattice"], c["dims"], c["periodic"], precision, "AA") for c in cases]
+        self.rhs = [make_rheology(c["op"], c["nu_p"], c["sigma_y"], c.get("m", 0.0), c["g"], **rh_kw)
+                    for c in cases]
+        self.count = len(cases)
+        self.N = [int(np.prod(c["dims"])) for c in cases]
+        self.c, self.w, self.opp = lbm_lattice_info(self.descs[0].lattice)
+        self.q = len(self.w)
+        sz = lbm_batch_query_sizes(self.descs, self.rhs)
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        alloc = lambda n: torch.empty(max(int(n), 256), dtype=torch.uint8, device=self.device)
+        self.pdf = alloc(sz.pdf_bytes)
+        self.tau = alloc(sz.tau_bytes) if sz.tau_bytes else None
+        self.work = alloc(sz.work_bytes)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.h = lbm_batch_create(self.descs, self.rhs)
+        lbm_batch_bind(self.h, self.pdf.data_ptr(), self.tau.data_ptr() if self.tau is not None else None,
+                       self.work.data_ptr(), self.stream.cuda_stream)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lbm_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, n=1):
+        lbm_batch_step(self.h, n)
+
+    @property
+    def time(self):
+        return lbm_batch_time(self.h)
+
+    def moments(self, sim):
+        return lbm_batch_read_moments(self.h, sim, self.N[sim])
+
+    def write_populations(self, sim, P, tau=None):
+        lbm_batch_write_populations(self.h, sim, P, tau)
+
+    def read_populations(self, sim, with_tau=False):
+        return lbm_batch_read_populations(self.h, sim, self.q, self.N[sim], with_tau)
+
+    def monitors(self):
+        return lbm_batch_monitors(self.h, self.count)
+
+    def set_monitor_interval(self, k):
+        lbm_batch_set_monitor_interval(self.h, k)
+
+    def history(self):
+        return lbm_batch_read_history(self.h, self.count)
+
+    def set_graph_steps(self, n):
+        lbm_batch_set_graph_steps(self.h, n)
+
+    def tiles(self):
+        return lbm_batch_get_tiles(self.h, self.count)
+
+    def autotune(self, trial_steps=10):
+        lbm_batch_autotune(self.h, trial_steps)
