@@ -105,6 +105,16 @@ typedef struct {
     int64_t unyielded;      /* IR: T <= sqrt2 sigma_y; PR: rho nu_app gamma_dot < sigma_y */
     int64_t fallback_nodes; /* nodes recomputed in FP64 (reduced precision)   */
     int64_t nonfinite;      /* fluid nodes with a non-finite rho or u         */
+    /* Convergence towards a steady state (the velocity-change criteria of
+     * Sec. 4.3 and 4.5): with u_prev each fluid node's output velocity at
+     * the previous fused monitor record (zero after lbm_init_equilibrium,
+     * lbm_set_mask or lbm_write_populations),
+     *   residual = sum |u - u_prev|^2 / sum |u|^2   (0 when sum |u|^2 = 0),
+     *   du_max   = max |u - u_prev|.
+     * Fused records then store u as the next u_prev; lbm_monitors compares
+     * with the last fused record's velocity and stores nothing. */
+    double residual;
+    double du_max;
 } lbm_monitor;
 
 typedef struct {
@@ -183,7 +193,8 @@ int lbm_read_moments(lbm_domain* dom, double* rho, double* u, double* nu_app,
                      uint8_t* unyielded);
 
 /* Checkpoint: the blob holds a header (descriptor, rheology, time, scheme
- * phase), the raw population storage, the PR field and the mask.  With
+ * phase), the raw population storage, the PR field, the mask and the
+ * residual monitor's reference velocity.  With
  * blob == NULL, lbm_save only reports the size in *bytes.  lbm_load rejects
  * (LBM_EFORMAT) a blob that is truncated or was saved from a domain with a
  * different descriptor.  Both synchronise. */

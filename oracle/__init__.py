@@ -90,6 +90,7 @@ def lib():
         L.orc_time.restype = ctypes.c_int64
         L.orc_moments.argtypes = [ctypes.c_void_p, dp, dp, dp, ctypes.POINTER(ctypes.c_uint8)]
         L.orc_monitors.argtypes = [ctypes.c_void_p, dp, ctypes.POINTER(ctypes.c_int64)]
+        L.orc_residual.argtypes = [ctypes.c_void_p, dp, ctypes.c_int, dp]
         _lib = L
     return _lib
 
@@ -218,3 +219,11 @@ class Domain:
         lib().orc_monitors(self._h, _dp(out), cnt.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
         return {"flux": out[0:3].copy(), "mass": out[3], "umax": out[4],
                 "unyielded": int(cnt[0]), "nonfinite": int(cnt[1]), "fluid": int(cnt[2])}
+
+    def residual(self, uprev, record=True):
+        """Residual and max velocity change against uprev (3*N, component-
+        major); with record, uprev is overwritten by the current velocity."""
+        assert uprev.dtype == np.float64 and uprev.size == 3 * self.N and uprev.flags.c_contiguous
+        out = np.zeros(2)
+        lib().orc_residual(self._h, _dp(uprev), int(bool(record)), _dp(out))
+        return {"residual": out[0], "du_max": out[1]}

@@ -581,3 +581,30 @@ void orc_monitors(const orc_domain* dom, double* out, int64_t* counts)
     counts[2] = nfl;
     free(rho); free(u); free(uy);
 }
+
+/* Convergence of the velocity field between two records, the quantity the
+ * steady-state criteria of Sec. 4.3 and 4.5 watch. */
+void orc_residual(const orc_domain* dom, double* uprev, int record, double* out)
+{
+    double* u = (double*)malloc(sizeof(double) * 3 * (size_t)dom->N);
+    orc_moments(dom, NULL, u, NULL, NULL);
+    double num = 0.0, den = 0.0, dmax = 0.0;
+    for (int64_t n = 0; n < dom->N; ++n) {
+        if (dom->solid[n]) continue;
+        double d2 = 0.0, u2 = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            const double ua = u[a * dom->N + n];
+            const double da = ua - uprev[a * dom->N + n];
+            d2 += da * da;
+            u2 += ua * ua;
+        }
+        num += d2;
+        den += u2;
+        if (sqrt(d2) > dmax) dmax = sqrt(d2);
+    }
+    out[0] = den > 0.0 ? num / den : 0.0;
+    out[1] = dmax;
+    if (record)
+        for (int64_t j = 0; j < 3 * dom->N; ++j) uprev[j] = dom->solid[j % dom->N] ? 0.0 : u[j];
+    free(u);
+}

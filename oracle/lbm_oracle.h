@@ -93,6 +93,11 @@ void orc_moments(const orc_domain* dom, double* rho, double* u, double* nu_app,
  * out[3] = total mass, out[4] = max |u|.  counts[0] = unyielded fluid nodes,
  * counts[1] = non-finite fluid nodes, counts[2] = fluid nodes. */
 void orc_monitors(const orc_domain* dom, double* out, int64_t* counts);
+/* Steady-state residual of the current output velocity u against a kept
+ * earlier one, uprev[3*N] (component-major), over fluid nodes:
+ * out[0] = sum |u - uprev|^2 / sum |u|^2 (0 when sum |u|^2 = 0),
+ * out[1] = max |u - uprev|.  With record != 0, uprev is then set to u. */
+void orc_residual(const orc_domain* dom, double* uprev, int record, double* out);
 
 #ifdef __cplusplus
 }

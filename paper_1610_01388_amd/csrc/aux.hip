@@ -135,6 +135,7 @@ __global__ __launch_bounds__(256) void k_readout(const NodeArgs a)
             v[MP_UNYIELDED] = pr.unyielded ? 1.0 : 0.0;
             v[MP_NONFINITE] = bad ? 1.0 : 0.0;
             v[MP_FLUID] = 1.0;
+            if (a.uprev) residual_terms(ux, uy, uz, bad, a.uprev + k, a.S, v);
         }
         block_reduce_store<MP_COUNT>(v, a.partials + (int64_t)blockIdx.x * MP_COUNT);
         return;
@@ -254,7 +255,23 @@ struct MonitorRecord {
     double mass;
     double umax;
     int64_t fluid_nodes, unyielded, fallback_nodes, nonfinite;
+    double residual, du_max;
 };
+
+__device__ __forceinline__ void fill_record(MonitorRecord* rec, const double (&r)[MP_COUNT], double ntotal)
+{
+    rec->flux[0] = r[MP_UX] / ntotal;
+    rec->flux[1] = r[MP_UY] / ntotal;
+    rec->flux[2] = r[MP_UZ] / ntotal;
+    rec->mass = r[MP_MASS];
+    rec->umax = r[MP_UMAX];
+    rec->fluid_nodes = (int64_t)r[MP_FLUID];
+    rec->unyielded = (int64_t)r[MP_UNYIELDED];
+    rec->fallback_nodes = (int64_t)r[MP_FALLBACK];
+    rec->nonfinite = (int64_t)r[MP_NONFINITE];
+    rec->residual = r[MP_U2] > 0.0 ? r[MP_DU2] / r[MP_U2] : 0.0;
+    rec->du_max = r[MP_DUMAX];
+}
 
 __global__ __launch_bounds__(256) void k_finalize(const double* parts, int64_t np, MonitorRecord* rec,
                                                   int64_t step, double ntotal)
@@ -267,7 +284,7 @@ __global__ __launch_bounds__(256) void k_finalize(const double* parts, int64_t n
 #pragma unroll
         for (int k = 0; k < MP_COUNT; ++k) {
             const double o = parts[j * MP_COUNT + k];
-            v[k] = (k == MP_UMAX) ? fmax(v[k], o) : v[k] + o;
+            v[k] = mp_is_max(k) ? fmax(v[k], o) : v[k] + o;
         }
     }
 #pragma unroll
@@ -277,22 +294,14 @@ __global__ __launch_bounds__(256) void k_finalize(const double* parts, int64_t n
         if ((int)threadIdx.x < s) {
 #pragma unroll
             for (int k = 0; k < MP_COUNT; ++k)
-                red[threadIdx.x][k] = (k == MP_UMAX) ? fmax(red[threadIdx.x][k], red[threadIdx.x + s][k])
+                red[threadIdx.x][k] = mp_is_max(k) ? fmax(red[threadIdx.x][k], red[threadIdx.x + s][k])
                                                      : red[threadIdx.x][k] + red[threadIdx.x + s][k];
         }
         __syncthreads();
     }
     if (threadIdx.x == 0) {
         rec->step = step;
-        rec->flux[0] = red[0][MP_UX] / ntotal;
-        rec->flux[1] = red[0][MP_UY] / ntotal;
-        rec->flux[2] = red[0][MP_UZ] / ntotal;
-        rec->mass = red[0][MP_MASS];
-        rec->umax = red[0][MP_UMAX];
-        rec->fluid_nodes = (int64_t)red[0][MP_FLUID];
-        rec->unyielded = (int64_t)red[0][MP_UNYIELDED];
-        rec->fallback_nodes = (int64_t)red[0][MP_FALLBACK];
-        rec->nonfinite = (int64_t)red[0][MP_NONFINITE];
+        fill_record(rec, red[0], ntotal);
     }
 }
 
@@ -311,7 +320,7 @@ __global__ __launch_bounds__(256) void k_batch_finalize(const double* parts, con
     for (int j = threadIdx.x; j < sm.nitems; j += 256) {
         const double* p = parts + (int64_t)(sm.item0 + j) * MP_COUNT;
 #pragma unroll
-        for (int k = 0; k < MP_COUNT; ++k) v[k] = (k == MP_UMAX) ? fmax(v[k], p[k]) : v[k] + p[k];
+        for (int k = 0; k < MP_COUNT; ++k) v[k] = mp_is_max(k) ? fmax(v[k], p[k]) : v[k] + p[k];
     }
 #pragma unroll
     for (int k = 0; k < MP_COUNT; ++k) red[threadIdx.x][k] = v[k];
@@ -320,7 +329,7 @@ __global__ __launch_bounds__(256) void k_batch_finalize(const double* parts, con
         if ((int)threadIdx.x < s) {
 #pragma unroll
             for (int k = 0; k < MP_COUNT; ++k)
-                red[threadIdx.x][k] = (k == MP_UMAX) ? fmax(red[threadIdx.x][k], red[threadIdx.x + s][k])
+                red[threadIdx.x][k] = mp_is_max(k) ? fmax(red[threadIdx.x][k], red[threadIdx.x + s][k])
                                                      : red[threadIdx.x][k] + red[threadIdx.x + s][k];
         }
         __syncthreads();
@@ -330,15 +339,7 @@ __global__ __launch_bounds__(256) void k_batch_finalize(const double* parts, con
         MonitorRecord* rec = records + (c % capacity) * nsims + sim;
         const double ntotal = (double)sm.N;
         rec->step = c;  // record number; the host maps it to the time step
-        rec->flux[0] = red[0][MP_UX] / ntotal;
-        rec->flux[1] = red[0][MP_UY] / ntotal;
-        rec->flux[2] = red[0][MP_UZ] / ntotal;
-        rec->mass = red[0][MP_MASS];
-        rec->umax = red[0][MP_UMAX];
-        rec->fluid_nodes = (int64_t)red[0][MP_FLUID];
-        rec->unyielded = (int64_t)red[0][MP_UNYIELDED];
-        rec->fallback_nodes = (int64_t)red[0][MP_FALLBACK];
-        rec->nonfinite = (int64_t)red[0][MP_NONFINITE];
+        fill_record(rec, red[0], ntotal);
     }
 }
 

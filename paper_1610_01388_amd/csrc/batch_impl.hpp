@@ -95,7 +95,9 @@ __device__ __forceinline__ void batch_tile(const BatchArgs& a, const BatchSim& s
         }
         if constexpr (OP == OP_PR) tau[n] = (T)pr.tau_p;
     }
-    if constexpr (MON) monitor_block<C>(active, mo, pr, cp, used_fb, a.partials + (int64_t)item * MP_COUNT);
+    if constexpr (MON)
+        monitor_block<C>(active, mo, pr, cp, used_fb, a.partials + (int64_t)item * MP_COUNT,
+                         a.uprev ? a.uprev + sm.off_u : nullptr, n, N);
 }
 
 template <int LAT, int PREC, int PAT, bool MON>

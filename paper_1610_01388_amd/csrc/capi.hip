@@ -52,6 +52,7 @@ struct MonitorRecord {
     double mass;
     double umax;
     int64_t fluid_nodes, unyielded, fallback_nodes, nonfinite;
+    double residual, du_max;
 };
 static_assert(sizeof(MonitorRecord) == sizeof(lbm_monitor), "record layout must match lbm_monitor");
 static_assert((int)LAYOUT_COMPACT == (int)LBM_COMPACT && (int)LAYOUT_DENSE == (int)LBM_DENSE,
@@ -66,7 +67,7 @@ int lattice_d(int lat) { return lat == 0 ? 2 : 3; }
 size_t prec_bytes(int p) { return p == LBM_FP64 ? 8 : p == LBM_FP32 ? 4 : 2; }
 
 struct Layout {
-    size_t pdf_copy, pdf, tau, mask, part, hist, rec, stage, work;
+    size_t pdf_copy, pdf, tau, mask, part, hist, rec, uprev, stage, work;
     size_t bits_off, base_off, mask_compact;  // compact mask: bitmap then word bases
     int64_t max_parts, npad;
     int W;
@@ -123,7 +124,8 @@ Layout layout_of(const lbm_desc* d, const lbm_rheology* r)
     L.part = 0;
     L.hist = align_up((size_t)L.max_parts * MP_COUNT * sizeof(double));
     L.rec = L.hist + align_up(kHistory * sizeof(MonitorRecord));
-    L.stage = L.rec + align_up(sizeof(MonitorRecord));
+    L.uprev = L.rec + align_up(sizeof(MonitorRecord));
+    L.stage = L.uprev + align_up((size_t)3 * L.npad * sizeof(double));
     size_t stage = std::min(kStageMax, align_up((size_t)N * (Q + 1) * 8));
     stage = std::max(stage, align_up((size_t)(Q + 1) * 8 * 256));
     L.work = L.stage + stage;
@@ -238,6 +240,7 @@ NodeArgs node_args(lbm_domain* dm)
     a.tau = dm->tau;
     a.mask = dm->mask;
     a.partials = (double*)dm->work;
+    a.uprev = (const double*)(dm->work + dm->L.uprev);
     a.N = dm->N;
     a.nx = dm->d.nx;
     a.ny = dm->d.ny;
@@ -267,6 +270,7 @@ StepArgs step_args(lbm_domain* dm)
     a.W = dm->L.W;
     a.S = dm->S;
     a.partials = (double*)dm->work;
+    a.uprev = (double*)(dm->work + dm->L.uprev);
     a.N = dm->N;
     a.nx = dm->d.nx;
     a.ny = dm->d.ny;
@@ -293,6 +297,14 @@ int need_bound(lbm_domain* dm)
 {
     if (!dm) return fail(LBM_EINVAL, "domain is NULL");
     if (!dm->bound) return fail(LBM_ESTATE, "domain has no bound buffers (call lbm_bind)");
+    return LBM_OK;
+}
+
+// The residual monitor's reference velocity restarts from zero whenever the
+// state is replaced (initialisation, mask, populations written).
+int clear_uprev(lbm_domain* dm)
+{
+    HIPCHK(hipMemsetAsync(dm->work + dm->L.uprev, 0, (size_t)3 * dm->L.npad * sizeof(double), dm->stream));
     return LBM_OK;
 }
 
@@ -481,7 +493,7 @@ int lbm_init_equilibrium(lbm_domain* dm, double rho0, const double* u0)
     NodeArgs a = node_args(dm);
     for (int k = 0; k < 3; ++k) a.u0[k] = u0 ? u0[k] : 0.0;
     HIPCHK(launch_init(dm->d.lattice, dm->r.op, dm->d.precision, a, rho0, dm->stream));
-    return LBM_OK;
+    return clear_uprev(dm);
 }
 
 int lbm_write_populations(lbm_domain* dm, const double* host_P, const double* host_tau)
@@ -490,6 +502,7 @@ int lbm_write_populations(lbm_domain* dm, const double* host_P, const double* ho
     if (rc) return rc;
     if (!host_P) return fail(LBM_EINVAL, "host_P is NULL");
     if (dm->d.scheme == LBM_AA) dm->parity = 0;  // written as post-collision, swapped
+    if ((rc = clear_uprev(dm))) return rc;
     const int Q = dm->Q;
     const int64_t chunk = chunk_nodes(dm, (size_t)(Q + 1) * 8);
     double* stage = (double*)(dm->work + dm->L.stage);
@@ -645,8 +658,9 @@ struct CkptHeader {
     lbm_rheology rh;
     int64_t t, stride, fluid;
     int32_t parity, q;
-    uint64_t pdf_bytes, tau_bytes, mask_bytes;
+    uint64_t pdf_bytes, tau_bytes, mask_bytes, uprev_bytes;
 };
+constexpr uint32_t kCkptVersion = 2;
 const char kMagic[8] = {'L', 'B', 'M', 'C', 'K', 'P', 'T', '1'};
 }  // namespace
 
@@ -657,7 +671,7 @@ int lbm_save(lbm_domain* dm, void* blob, size_t* bytes)
     if (!bytes) return fail(LBM_EINVAL, "bytes is NULL");
     CkptHeader h{};
     memcpy(h.magic, kMagic, 8);
-    h.version = 1;
+    h.version = kCkptVersion;
     h.header_bytes = sizeof(CkptHeader);
     h.desc = dm->d;
     h.rh = dm->r;
@@ -669,7 +683,8 @@ int lbm_save(lbm_domain* dm, void* blob, size_t* bytes)
     h.pdf_bytes = (uint64_t)dm->Q * dm->S * prec_bytes(dm->d.precision);
     h.tau_bytes = dm->tau ? (uint64_t)dm->S * (dm->d.precision == LBM_FP64 ? 8 : 4) : 0;
     h.mask_bytes = dm->d.layout == LBM_DENSE ? (uint64_t)dm->N : (uint64_t)dm->L.mask_compact;
-    const size_t need = sizeof(h) + h.pdf_bytes + h.tau_bytes + h.mask_bytes;
+    h.uprev_bytes = (uint64_t)3 * dm->S * sizeof(double);
+    const size_t need = sizeof(h) + h.pdf_bytes + h.tau_bytes + h.mask_bytes + h.uprev_bytes;
     if (!blob) {
         *bytes = need;
         return LBM_OK;
@@ -685,6 +700,9 @@ int lbm_save(lbm_domain* dm, void* blob, size_t* bytes)
     if (h.tau_bytes) HIPCHK(hipMemcpy(p, dm->tau, h.tau_bytes, hipMemcpyDeviceToHost));
     p += h.tau_bytes;
     HIPCHK(hipMemcpy(p, dm->mask, h.mask_bytes, hipMemcpyDeviceToHost));
+    p += h.mask_bytes;
+    // the residual monitor's reference velocity: components at 0, S, 2S
+    HIPCHK(hipMemcpy(p, dm->work + dm->L.uprev, h.uprev_bytes, hipMemcpyDeviceToHost));
     *bytes = need;
     return LBM_OK;
 }
@@ -697,7 +715,7 @@ int lbm_load(lbm_domain* dm, const void* blob, size_t bytes)
     CkptHeader h;
     if (bytes < sizeof h) return fail(LBM_EFORMAT, "checkpoint truncated (header)");
     memcpy(&h, blob, sizeof h);
-    if (memcmp(h.magic, kMagic, 8) != 0 || h.version != 1 || h.header_bytes != sizeof h)
+    if (memcmp(h.magic, kMagic, 8) != 0 || h.version != kCkptVersion || h.header_bytes != sizeof h)
         return fail(LBM_EFORMAT, "not a checkpoint of this library version");
     if (memcmp(&h.desc, &dm->d, sizeof(lbm_desc)) != 0 || h.q != dm->Q)
         return fail(LBM_EFORMAT, "checkpoint was saved from a different domain descriptor");
@@ -706,9 +724,10 @@ int lbm_load(lbm_domain* dm, const void* blob, size_t bytes)
         return fail(LBM_EFORMAT, "checkpoint stride does not fit the domain");
     const uint64_t tau_expect = dm->tau ? (uint64_t)h.stride * (dm->d.precision == LBM_FP64 ? 8 : 4) : 0;
     if (h.pdf_bytes != (uint64_t)dm->Q * h.stride * prec_bytes(dm->d.precision) || h.tau_bytes != tau_expect ||
-        h.mask_bytes != mask_expect)
+        h.mask_bytes != mask_expect || h.uprev_bytes != (uint64_t)3 * h.stride * sizeof(double))
         return fail(LBM_EFORMAT, "checkpoint sizes do not match the domain");
-    if (bytes < sizeof h + h.pdf_bytes + h.tau_bytes + h.mask_bytes) return fail(LBM_EFORMAT, "checkpoint truncated");
+    if (bytes < sizeof h + h.pdf_bytes + h.tau_bytes + h.mask_bytes + h.uprev_bytes)
+        return fail(LBM_EFORMAT, "checkpoint truncated");
     const char* p = (const char*)blob + sizeof h;
     HIPCHK(hipStreamSynchronize(dm->stream));
     dm->cur = 0;
@@ -717,6 +736,8 @@ int lbm_load(lbm_domain* dm, const void* blob, size_t bytes)
     if (h.tau_bytes) HIPCHK(hipMemcpy(dm->tau, p, h.tau_bytes, hipMemcpyHostToDevice));
     p += h.tau_bytes;
     HIPCHK(hipMemcpy(dm->mask, p, h.mask_bytes, hipMemcpyHostToDevice));
+    p += h.mask_bytes;
+    HIPCHK(hipMemcpy(dm->work + dm->L.uprev, p, h.uprev_bytes, hipMemcpyHostToDevice));
     dm->t = h.t;
     dm->S = h.stride;
     dm->Nf = h.fluid;
@@ -837,7 +858,7 @@ namespace {
 constexpr int kBatchHistory = 256;
 
 struct BatchLayout {
-    size_t pdf, tau, sims, work_list, parts, recs, counter, stage, total;
+    size_t pdf, tau, sims, work_list, parts, recs, counter, uprev, stage, total;
 };
 
 }  // namespace
@@ -891,7 +912,7 @@ int batch_plan(lbm_batch* b)
 {
     b->sims.assign(b->count, BatchSim{});
     b->work.clear();
-    int64_t off_pdf = 0, off_tau = 0;
+    int64_t off_pdf = 0, off_tau = 0, off_u = 0;
     for (int k = 0; k < b->count; ++k) {
         BatchSim& s = b->sims[k];
         const lbm_desc& d = b->d[k];
@@ -911,8 +932,10 @@ int batch_plan(lbm_batch* b)
         s.N = (int64_t)d.nx * d.ny * d.nz;
         s.off_pdf = off_pdf;
         s.off_tau = off_tau;
+        s.off_u = off_u;
         off_pdf += (s.N * b->Q + 63) / 64 * 64;
         off_tau += (s.N + 63) / 64 * 64;
+        off_u += 3 * ((s.N + 63) / 64 * 64);
         s.cd = make_coll<double>(b->r[k]);
         s.cf = make_coll<float>(b->r[k]);
     }
@@ -927,7 +950,8 @@ int batch_plan(lbm_batch* b)
     L.parts = L.work_list + align_up(sizeof(int) * b->nitems);
     L.recs = L.parts + align_up((size_t)b->nitems * MP_COUNT * sizeof(double));
     L.counter = L.recs + align_up((size_t)kBatchHistory * b->count * sizeof(MonitorRecord));
-    L.stage = L.counter + kAlign;
+    L.uprev = L.counter + kAlign;
+    L.stage = L.uprev + align_up((size_t)off_u * sizeof(double));
     int64_t maxN = 0;
     for (auto& s : b->sims) maxN = std::max(maxN, s.N);
     size_t stage = std::min(kStageMax, align_up((size_t)maxN * (b->Q + 1) * 8));
@@ -953,6 +977,7 @@ BatchArgs batch_args(lbm_batch* b)
     a.pdf = b->pdf;
     a.tau = b->tau;
     a.partials = (double*)(b->workbuf + b->L.parts);
+    a.uprev = (double*)(b->workbuf + b->L.uprev);
     a.h16_scale = std::ldexp(1.0f, -b->r[0].fp16_scale_log2);
     a.h16_inv = std::ldexp(1.0f, b->r[0].fp16_scale_log2);
     a.fallback = (b->prec != LBM_FP64 && b->r[0].fp64_fallback) ? 1 : 0;
@@ -1022,6 +1047,7 @@ NodeArgs batch_node_args(lbm_batch* b, int k)
     if (b->r[k].op != LBM_PR) a.tau = nullptr;
     a.mask = nullptr;
     a.partials = (double*)(b->workbuf + b->L.parts);
+    a.uprev = (const double*)(b->workbuf + b->L.uprev) + s.off_u;
     a.N = s.N;
     a.S = s.N;
     a.nx = s.nx; a.ny = s.ny; a.nz = s.nz;
@@ -1136,6 +1162,7 @@ int lbm_batch_init_equilibrium(lbm_batch* b)
     b->mon_times.clear();
     b->hist_read = 0;
     HIPCHK(hipMemsetAsync(b->workbuf + b->L.counter, 0, sizeof(int64_t), b->stream));
+    HIPCHK(hipMemsetAsync(b->workbuf + b->L.uprev, 0, b->L.stage - b->L.uprev, b->stream));
     for (int k = 0; k < b->count; ++k) {
         NodeArgs a = batch_node_args(b, k);
         HIPCHK(launch_init(b->lat, b->r[k].op, b->prec, a, b->r[k].rho0, b->stream));
@@ -1151,6 +1178,8 @@ int lbm_batch_write_populations(lbm_batch* b, int32_t sim, const double* host_P,
     if (!host_P) return fail(LBM_EINVAL, "host_P is NULL");
     if (b->parity != 0) return fail(LBM_ESTATE, "write populations only between step pairs (even time)");
     const BatchSim& s = b->sims[sim];
+    HIPCHK(hipMemsetAsync(b->workbuf + b->L.uprev + (size_t)s.off_u * sizeof(double), 0,
+                          (size_t)3 * s.N * sizeof(double), b->stream));
     const int Q = b->Q;
     const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(s.N, (int64_t)((b->L.total - b->L.stage) / ((Q + 1) * 8))));
     double* stage = (double*)(b->workbuf + b->L.stage);

@@ -48,6 +48,19 @@ __device__ __forceinline__ int wrap_halo(int g, int n, int per, bool& out)
     return g;
 }
 
+// Residual terms of one node: |u - u_prev|^2, |u|^2 and |u - u_prev|, with
+// u_prev the velocity stored at the previous fused monitor (three entries
+// `stride` apart).
+__device__ __forceinline__ void residual_terms(double ux, double uy, double uz, bool bad, const double* up,
+                                               int64_t stride, double (&v)[MP_COUNT])
+{
+    const double d0 = ux - up[0], d1 = uy - up[stride], d2 = uz - up[2 * stride];
+    const double du2 = d0 * d0 + d1 * d1 + d2 * d2;
+    v[MP_DU2] = du2;
+    v[MP_U2] = ux * ux + uy * uy + uz * uz;
+    v[MP_DUMAX] = bad ? INFINITY : sqrt(du2);
+}
+
 template <int N>
 __device__ __forceinline__ void block_reduce_store(double (&v)[N], double* dst)
 {
@@ -59,7 +72,7 @@ __device__ __forceinline__ void block_reduce_store(double (&v)[N], double* dst)
 #pragma unroll
         for (int k = 0; k < N; ++k) {
             const double o = __shfl_xor(v[k], off, 64);
-            v[k] = (k == MP_UMAX) ? fmax(v[k], o) : v[k] + o;
+            v[k] = mp_is_max(k) ? fmax(v[k], o) : v[k] + o;
         }
     }
     if (lane == 0) {
@@ -71,7 +84,7 @@ __device__ __forceinline__ void block_reduce_store(double (&v)[N], double* dst)
         const int nw = (blockDim.x + 63) >> 6;
         for (int k = 0; k < N; ++k) {
             double s = red[0][k];
-            for (int w = 1; w < nw; ++w) s = (k == MP_UMAX) ? fmax(s, red[w][k]) : s + red[w][k];
+            for (int w = 1; w < nw; ++w) s = mp_is_max(k) ? fmax(s, red[w][k]) : s + red[w][k];
             dst[k] = s;
         }
     }

@@ -23,8 +23,15 @@ namespace lbm {
 enum { PAT_AB = 0, PAT_AA_PULL = 1, PAT_AA_LOCAL = 2 };
 enum { PREC_F64 = 0, PREC_F32 = 1, PREC_F16 = 2 };
 
-// Per-block monitor partial sums (doubles, fixed order).
-enum { MP_UX = 0, MP_UY, MP_UZ, MP_MASS, MP_UMAX, MP_UNYIELDED, MP_FALLBACK, MP_NONFINITE, MP_FLUID, MP_COUNT };
+// Per-block monitor partial sums (doubles, fixed order).  MP_DU2 and MP_U2
+// are the sums of |u - u_prev|^2 and |u|^2 behind the convergence residual,
+// u_prev being the output velocity at the previous fused monitor step.
+enum {
+    MP_UX = 0, MP_UY, MP_UZ, MP_MASS, MP_UMAX, MP_UNYIELDED, MP_FALLBACK, MP_NONFINITE, MP_FLUID,
+    MP_DU2, MP_U2, MP_DUMAX, MP_COUNT
+};
+// partials combine by max for these entries and by addition for the others
+__host__ __device__ constexpr bool mp_is_max(int k) { return k == MP_UMAX || k == MP_DUMAX; }
 
 // Population storage layouts.
 //  LAYOUT_DENSE:   every node has a slot; slot (i, n) at i*S + n with S = N;
@@ -46,6 +53,7 @@ struct StepArgs {
     const uint64_t* bits;  // compact: fluid bitmap [row][W]
     const uint32_t* wbase; // compact: [row][W]
     double* partials;      // MON: MP_COUNT doubles per tile
+    double* uprev;         // MON: output velocity of the previous fused monitor, [3][S]; overwritten
     int64_t N;             // nodes
     int64_t S;             // direction stride of the population arrays
     int W;                 // compact: words per row
@@ -73,6 +81,7 @@ struct NodeArgs {
     int W;
     int compact;
     double* partials;      // monitors on demand
+    const double* uprev;   // monitors on demand: residual against it ([3][S], read only)
     double* out;           // staging (layout depends on the kernel)
     uint8_t* out_flags;
     int64_t N, n0, count;  // nodes [n0, n0 + count)
@@ -100,6 +109,7 @@ struct BatchSim {
     int64_t N;             // nodes
     int64_t off_pdf;       // element offset of the simulation's population block ([i][n], stride N)
     int64_t off_tau;       // element offset of its relaxation-time block (PR)
+    int64_t off_u;         // element offset of its previous-velocity block ([3][N] doubles)
     Coll<double> cd;
     Coll<float> cf;
 };
@@ -111,6 +121,7 @@ struct BatchArgs {
     void* pdf;             // arena (AA: one copy)
     void* tau;
     double* partials;      // MON: MP_COUNT per work item
+    double* uprev;         // MON: previous-velocity blocks (BatchSim::off_u)
     float h16_scale, h16_inv;
     int fallback;
 };

@@ -48,10 +48,14 @@ __device__ __forceinline__ void collide_node(typename Store<PREC>::C (&h)[Lattic
     relax<LAT, OP>(h, mo, pr, cp);
 }
 
-// Per-block monitor partial sums of the state the step started from.
+// Per-block monitor partial sums of the state the step started from.  With
+// uprev set, the node's output velocity is compared with the one stored at
+// the previous fused monitor (slot idx, components stride apart) and then
+// replaces it.
 template <class C>
 __device__ __forceinline__ void monitor_block(bool active, const Moments<C>& mo, const Pre<C>& pr,
-                                              const Coll<C>& cp, bool used_fb, double* dst)
+                                              const Coll<C>& cp, bool used_fb, double* dst, double* uprev,
+                                              int64_t idx, int64_t stride)
 {
     double v[MP_COUNT];
 #pragma unroll
@@ -70,6 +74,13 @@ __device__ __forceinline__ void monitor_block(bool active, const Moments<C>& mo,
         v[MP_FALLBACK] = used_fb ? 1.0 : 0.0;
         v[MP_NONFINITE] = bad ? 1.0 : 0.0;
         v[MP_FLUID] = 1.0;
+        if (uprev) {
+            double* up = uprev + idx;
+            residual_terms(ux, uy, uz, bad, up, stride, v);
+            up[0] = ux;
+            up[stride] = uy;
+            up[2 * stride] = uz;
+        }
     }
     block_reduce_store<MP_COUNT>(v, dst);
 }
@@ -188,7 +199,8 @@ __global__ __launch_bounds__(256) void k_step(const StepArgs a)
         if constexpr (OP == OP_PR) ((T*)a.tau)[n] = (T)pr.tau_p;
     }
 
-    if constexpr (MON) monitor_block<C>(active, mo, pr, cp, used_fb, a.partials + (int64_t)tile * MP_COUNT);
+    if constexpr (MON)
+        monitor_block<C>(active, mo, pr, cp, used_fb, a.partials + (int64_t)tile * MP_COUNT, a.uprev, n, a.N);
 }
 
 // Compact-layout step: only fluid nodes have population slots.  A wavefront
@@ -343,7 +355,8 @@ __global__ __launch_bounds__(256) void k_step_compact(const StepArgs a, const ui
         }
         if constexpr (OP == OP_PR) ((T*)a.tau)[k] = (T)pr.tau_p;
     }
-    if constexpr (MON) monitor_block<C>(active, mo, pr, cp, used_fb, a.partials + (int64_t)tile * MP_COUNT);
+    if constexpr (MON)
+        monitor_block<C>(active, mo, pr, cp, used_fb, a.partials + (int64_t)tile * MP_COUNT, a.uprev, k, St);
 }
 
 template <int LAT, int OP, int PREC, int PAT, bool MON>

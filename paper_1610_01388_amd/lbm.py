@@ -50,12 +50,13 @@ class lbm_monitor(ctypes.Structure):
     _fields_ = [("step", ctypes.c_int64), ("flux", ctypes.c_double * 3), ("mass", ctypes.c_double),
                 ("umax", ctypes.c_double), ("fluid_nodes", ctypes.c_int64),
                 ("unyielded", ctypes.c_int64), ("fallback_nodes", ctypes.c_int64),
-                ("nonfinite", ctypes.c_int64)]
+                ("nonfinite", ctypes.c_int64), ("residual", ctypes.c_double), ("du_max", ctypes.c_double)]
 
     def as_dict(self):
         return {"step": self.step, "flux": np.array(self.flux[:]), "mass": self.mass,
                 "umax": self.umax, "fluid": self.fluid_nodes, "unyielded": self.unyielded,
-                "fallback": self.fallback_nodes, "nonfinite": self.nonfinite}
+                "fallback": self.fallback_nodes, "nonfinite": self.nonfinite,
+                "residual": self.residual, "du_max": self.du_max}
 
 
 class lbm_sizes(ctypes.Structure):

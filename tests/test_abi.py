@@ -101,3 +101,28 @@ def test_unbound_domain_refuses_work():
         lbm.lbm_set_tile(h, 8, 8, 2)  # compact needs one wavefront per 64-node row segment
     lbm.lbm_set_tile(h, 64, 2, 2)
     lbm.lbm_destroy(h)
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """The ctypes mirrors of the ABI structs have the header's size and field
+    offsets (compiled with the host C compiler against include/lbm.h)."""
+    import ctypes
+    import subprocess
+    structs = {"lbm_desc": lbm.lbm_desc, "lbm_rheology": lbm.lbm_rheology, "lbm_monitor": lbm.lbm_monitor,
+               "lbm_sizes": lbm.lbm_sizes}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "lbm.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'printf("{name} size %zu\\n", sizeof({name}));')
+        for f in cls._fields_:
+            lines.append(f'printf("{name} {f[0]} %zu\\n", offsetof({name}, {f[0]}));')
+    lines.append("return 0; }")
+    src = tmp_path / "sizes.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "sizes"
+    subprocess.check_call(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    got = {(a, b): int(c) for a, b, c in (l.split() for l in out if l)}
+    for name, cls in structs.items():
+        assert got[(name, "size")] == ctypes.sizeof(cls), name
+        for f in cls._fields_:
+            assert got[(name, f[0])] == getattr(cls, f[0]).offset, (name, f[0])

@@ -109,6 +109,21 @@ def test_batch_monitors_through_replays():
         for mb, me in zip(rb, re):
             assert np.array_equal(mb["flux"], me["flux"]) and mb["mass"] == me["mass"]
             assert mb["unyielded"] == me["unyielded"] and mb["fluid"] == me["fluid"]
+            assert mb["residual"] == me["residual"] and mb["du_max"] == me["du_max"]
+    # residuals against the single-domain kernels' fused monitors (same records)
+    from paper_1610_01388_amd import lbm
+    for k in (0, 3):
+        c = CASES[k]
+        P, tau, perm = states[k]
+        d = lbm.Domain(c["lattice"], c["dims"], c["periodic"], c["op"], c["nu_p"], c["sigma_y"], m=c["m"], g=c["g"],
+                       layout="COMPACT")
+        d.write_populations(P[perm], tau if c["op"] == "PR" else None)
+        d.set_monitor_interval(10)
+        d.step(60)
+        hd = d.history()
+        for r, h in zip(hb, hd):
+            assert abs(r[k]["residual"] - h["residual"]) <= 1e-12 * h["residual"]
+            assert abs(r[k]["flux"][2] - h["flux"][2]) <= 1e-12 * abs(h["flux"][2]) + 1e-300
     now = b.monitors()
     for k, c in enumerate(CASES):
         assert now[k]["step"] == 60 and now[k]["fluid"] == int(np.prod(c["dims"])) and now[k]["nonfinite"] == 0

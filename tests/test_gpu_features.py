@@ -126,7 +126,13 @@ def test_fused_monitors_match_oracle_and_on_demand():
     dom.step(35)
     hist = dom.history()
     assert [h["step"] for h in hist] == [0, 10, 20, 30]
-    od.step(30)
+    uprev = np.zeros(3 * N)
+    for h in hist:  # residual against the previous record (zero before the first)
+        r = od.residual(uprev)
+        assert abs(h["residual"] - r["residual"]) <= 1e-9 * r["residual"]
+        assert abs(h["du_max"] - r["du_max"]) <= 1e-9 * r["du_max"]
+        if h["step"] < 30:
+            od.step(10)
     om = od.monitors()
     h = hist[-1]
     assert abs(h["flux"][2] - om["flux"][2]) <= 1e-12 * abs(om["flux"][2])
@@ -138,6 +144,9 @@ def test_fused_monitors_match_oracle_and_on_demand():
     assert now["step"] == 35
     assert abs(now["flux"][2] - om["flux"][2]) <= 1e-12 * abs(om["flux"][2])
     assert abs(now["umax"] - om["umax"]) <= 1e-12 * om["umax"]
+    r = od.residual(uprev, record=False)  # on demand: against the step-30 record, nothing stored
+    assert abs(now["residual"] - r["residual"]) <= 1e-9 * r["residual"]
+    assert dom.monitors()["residual"] == now["residual"]
 
 
 @pytest.mark.parametrize("layout", ["COMPACT", "DENSE"])
@@ -150,16 +159,25 @@ def test_checkpoint_resume_bitwise(op, layout):
     mk = lambda: lbm.Domain("D3Q27", dims, per, op, 0.1, 5e-4, m=1e4, g=(2e-5, 0, 0), layout=layout)
     a = mk()
     a.set_mask(mask)
+    a.set_monitor_interval(5)
     a.step(25)
+    a.history()
     blob = a.save()
     a.step(26)
     Pa, ta = a.read_populations(with_tau=op == "PR")
+    ha = a.history()
     b = mk()
     b.load(blob)
     assert b.time == 25
+    b.set_monitor_interval(5)
     b.step(26)
     Pb, tb = b.read_populations(with_tau=op == "PR")
+    hb = b.history()
     assert np.array_equal(Pa, Pb)
+    # the residual monitor's reference velocity travels with the checkpoint
+    assert [h["step"] for h in ha] == [h["step"] for h in hb] == [25, 30, 35, 40, 45, 50]
+    assert [h["residual"] for h in ha] == [h["residual"] for h in hb]
+    assert ha[0]["residual"] != 1.0  # a zero reference would give exactly 1
     if op == "PR":
         assert np.array_equal(ta, tb)
     with pytest.raises(lbm.LbmError) as e:

@@ -37,10 +37,12 @@ MUTATIONS = {
     "ir_unyielded_stress_sign": ("sig[a][b] = -Tdev[a][b];", "sig[a][b] = Tdev[a][b];"),
     "ir_relaxes_full_tensor": ("Tdev[a][b] = T[a][b] - ((a == b && a < L->d) ? tr / L->d : 0.0);",
                                "Tdev[a][b] = T[a][b];"),
+    "residual_reference_not_kept": ("    if (record)\n        for (int64_t j = 0;", "    if (0)\n        for (int64_t j = 0;"),
+    "residual_unsquared": ("        num += d2;", "        num += sqrt(d2);"),
 }
 
 PIN_TESTS = ["tests/test_oracle_lattice.py", "tests/test_oracle_operators.py",
-             "tests/test_oracle_flows.py"]
+             "tests/test_oracle_flows.py", "tests/test_oracle_residual.py"]
 
 
 @pytest.mark.parametrize("name", sorted(MUTATIONS))
