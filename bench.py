@@ -122,9 +122,10 @@ def run_form(torch, lbm, name, case, precision, mask, fluid, warmup, steps, ref=
     return out, mom
 
 
-def run_batch(torch, lbm, cases, precision, warmup, steps, autotune=True, graph_steps=100):
-    """The batched sweep: every case in one batch, stepped by graph replays
-    of one persistent launch per step; tiles picked by the autotuner."""
+def run_batch(torch, lbm, cases, precision, warmup, steps, autotune=True, graph_steps=1000):
+    """The batched sweep: every case in one batch, stepped by replays of one
+    captured graph of graph_steps persistent launches (one per step); tiles
+    and work-item order picked by the autotuner."""
     b = lbm.Batch(cases, precision=precision)
     if autotune:
         b.autotune(10)
@@ -141,20 +142,22 @@ def run_batch(torch, lbm, cases, precision, warmup, steps, autotune=True, graph_
     ms = e0.elapsed_time(e1)
     moms = [b.moments(k) for k in range(len(cases))]
     tiles = b.tiles()
+    sched = b.schedule()
     mons = b.monitors()
     b.close()
     torch.cuda.empty_cache()
-    return ms, moms, tiles, mons
+    return ms, moms, tiles, mons, sched
 
 
-def batch_form(torch, lbm, cases, warmup, steps):
+def batch_form(torch, lbm, cases, warmup, steps, graph_steps=1000):
     """FP32 batched sweep with its error against the FP64 batch of the same
-    cases (same steps from rest)."""
+    cases (same steps from rest).  Warmup and timed steps are whole graph
+    replays when they are multiples of graph_steps."""
     nodes = sum(int(np.prod(c["dims"])) for c in cases)
     bytes_step = sum(int(np.prod(c["dims"])) * algorithmic_bytes_per_node(c["lattice"], c["op"], "FP32")
                      for c in cases)
-    ms32, m32, tiles, mons = run_batch(torch, lbm, cases, "FP32", warmup, steps)
-    ms64, m64, _, _ = run_batch(torch, lbm, cases, "FP64", warmup, steps)
+    ms32, m32, tiles, mons, sched = run_batch(torch, lbm, cases, "FP32", warmup, steps, graph_steps=graph_steps)
+    ms64, m64, _, _, _ = run_batch(torch, lbm, cases, "FP64", warmup, steps, graph_steps=graph_steps)
     cat = lambda ms: (np.concatenate([m[0] for m in ms]), np.concatenate([m[1] for m in ms], axis=1), None,
                       np.concatenate([m[3] for m in ms]))
     err = compare(cat(m64), cat(m32), 2)
@@ -177,7 +180,8 @@ def batch_form(torch, lbm, cases, warmup, steps):
     return {"form": f"batched sweep: {len(cases)} D3Q19 ducts FP32", "lattice": "D3Q19", "precision": "FP32",
             "simulations": len(cases), "nodes": nodes, "steps": steps, "ms_per_step": ms32 / steps,
             "MLUPS": nodes * steps / (ms32 * 1e-3) / 1e6, "algorithmic_GBs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS,
-            "algorithmic_bytes_per_step": bytes_step, "graph_steps": 100, "tiles": shapes, "operators": ops,
+            "algorithmic_bytes_per_step": bytes_step, "graph_steps": graph_steps, "tiles": shapes,
+            "tile_policy": sched[0], "xcd_order": sched[1], "operators": ops,
             "fp64_batch_MLUPS": nodes * steps / (ms64 * 1e-3) / 1e6,
             "nonfinite_sims": int(sum(1 for m in mons if m["nonfinite"])),
             "error_vs_fp64": err}
@@ -242,7 +246,9 @@ def main():
 
     if args.batch_only:
         log(f"batched sweep only: warmup {args.warmup}, steps {args.steps}")
-        print(json.dumps(batch_form(torch, lbm, inputs.batch_sweep(), args.warmup, args.steps)), flush=True)
+        g = 1000 if args.steps % 1000 == 0 and args.warmup % 1000 == 0 else 100
+        print(json.dumps(batch_form(torch, lbm, inputs.batch_sweep(), args.warmup, args.steps, graph_steps=g)),
+              flush=True)
         return
 
     if args.copy_calibration:
@@ -341,8 +347,8 @@ def main():
         d64, dref = run_form(torch, lbm, "duct D3Q19 IR FP64", duct, "FP64", None, dfl, W, K)
         d32, _ = run_form(torch, lbm, "duct D3Q19 IR FP32", duct, "FP32", None, dfl, W, K, ref=dref)
         forms += [d64, d32]
-        log("forms: batched sweep, 256 D3Q19 ducts (sides 32..160, length 4), FP32 vs FP64")
-        forms.append(batch_form(torch, lbm, inputs.batch_sweep(), W, K))
+        log("forms: batched sweep, 256 D3Q19 ducts (sides 32..160, length 4), FP32 vs FP64, 1000-step graph")
+        forms.append(batch_form(torch, lbm, inputs.batch_sweep(), 1000, 1000))
     result["forms"] = forms
 
     if not args.no_cpu:

@@ -218,7 +218,7 @@ int lbm_destroy(lbm_domain* dom);
  * Every simulation is all-fluid inside its box (walls only through
  * non-periodic axes) and has its own sizes, operator and rheology; all
  * share one lattice, one precision, the AA scheme, the FP64-fallback flag
- * and the FP16 scale.  One step is one persistent kernel launch over a work
+ * and the FP16 scale; each holds fewer than 2^31 / Q nodes.  One step is one persistent kernel launch over a work
  * list of 256-node tiles of all simulations; lbm_batch_step replays a
  * captured hipGraph of graph_steps such launches when it can.  The update
  * of each node is the same as lbm_step's (a simulation gives bitwise the
@@ -258,9 +258,17 @@ int lbm_batch_step(lbm_batch* b, int64_t nsteps);
 int lbm_batch_time(lbm_batch* b, int64_t* t);
 /* Tile shape chosen for each simulation (3*count ints). */
 int lbm_batch_get_tiles(lbm_batch* b, int32_t* tiles);
-/* Time the tile policies (fewest padded nodes; 64-wide rows; fixed 64x4x1)
- * on trial_steps steps of the bound batch and keep the fastest; the state
- * is restored.  Synchronises. */
+/* Scheduling in use: tile policy (0 fewest padded nodes, 1 rows at least
+ * 64 wide, 2 fixed 64x4x1) and work-item order (0 plain grid stride over
+ * the list; 1, the default, one contiguous chunk of the list per XCD so
+ * that neighbouring tiles share an L2). */
+int lbm_batch_get_schedule(lbm_batch* b, int32_t* tile_policy, int32_t* xcd_order);
+/* Choose the scheduling by hand (the state is kept; results do not depend on
+ * it).  LBM_EINVAL outside the ranges above.  Synchronises. */
+int lbm_batch_set_schedule(lbm_batch* b, int32_t tile_policy, int32_t xcd_order);
+/* Time every tile policy with both work-item orders on trial_steps steps of
+ * the bound batch and keep the fastest; the state is restored.  The device
+ * layout does not depend on the choice.  Synchronises. */
 int lbm_batch_autotune(lbm_batch* b, int32_t trial_steps);
 int lbm_batch_destroy(lbm_batch* b);
 

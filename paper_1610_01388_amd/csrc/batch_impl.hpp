@@ -38,8 +38,10 @@ __device__ __forceinline__ void batch_tile(const BatchArgs& a, const BatchSim& s
     const int y = tty * sm.ty + ly;
     const int z = ttz * sm.tz + lz;
     const bool active = (x < sm.nx) & (y < sm.ny) & (z < sm.nz);
-    const int64_t N = sm.N;
-    const int64_t n = x + (int64_t)sm.nx * (y + (int64_t)sm.ny * z);
+    // indices inside one simulation fit 32 bits (Q * N < 2^31 is checked on
+    // the host)
+    const int N = (int)sm.N;
+    const int n = x + sm.nx * (y + sm.ny * z);
     const Coll<C>& cp = [&]() -> const Coll<C>& {
         if constexpr (PREC == PREC_F64) return sm.cd;
         else return sm.cf;
@@ -49,27 +51,35 @@ __device__ __forceinline__ void batch_tile(const BatchArgs& a, const BatchSim& s
     Pre<C> pr;
     bool used_fb = false;
     if (active) {
-        // neighbour x + s*c: its node index, or -1 beyond a wall face
-        auto nb = [&](int cx, int cy, int cz) -> int64_t {
-            int p0 = x + cx, p1 = y + cy, p2 = z + cz;
-            if (p0 < 0 || p0 >= sm.nx) { if (!sm.per[0]) return -1; p0 = p0 < 0 ? p0 + sm.nx : p0 - sm.nx; }
-            if (p1 < 0 || p1 >= sm.ny) { if (!sm.per[1]) return -1; p1 = p1 < 0 ? p1 + sm.ny : p1 - sm.ny; }
-            if (p2 < 0 || p2 >= sm.nz) { if (!sm.per[2]) return -1; p2 = p2 < 0 ? p2 + sm.nz : p2 - sm.nz; }
-            return p0 + (int64_t)sm.nx * (p1 + (int64_t)sm.ny * p2);
+        // Offset of the neighbour one step back / forward along each axis
+        // (periodic axes wrap), and wall bits: bit 0 = no neighbour at -1,
+        // bit 2 = none at +1.  A direction's neighbour is n plus the sum of
+        // its three axis offsets, unless one of its steps meets a wall.
+        const int sy = sm.nx, sz = sm.nx * sm.ny;
+        const int ox[3] = {x > 0 ? -1 : sm.nx - 1, 0, x < sm.nx - 1 ? 1 : 1 - sm.nx};
+        const int oy[3] = {y > 0 ? -sy : (sm.ny - 1) * sy, 0, y < sm.ny - 1 ? sy : (1 - sm.ny) * sy};
+        const int oz[3] = {z > 0 ? -sz : (sm.nz - 1) * sz, 0, z < sm.nz - 1 ? sz : (1 - sm.nz) * sz};
+        const unsigned wx = sm.per[0] ? 0u : (x == 0 ? 1u : 0u) | (x == sm.nx - 1 ? 4u : 0u);
+        const unsigned wy = sm.per[1] ? 0u : (y == 0 ? 1u : 0u) | (y == sm.ny - 1 ? 4u : 0u);
+        const unsigned wz = sm.per[2] ? 0u : (z == 0 ? 1u : 0u) | (z == sm.nz - 1 ? 4u : 0u);
+        // neighbour x + s c (s = +-1 folded into cx, cy, cz): node index or -1
+        auto nb = [&](int cx, int cy, int cz) -> int {
+            const bool wall = ((wx >> (cx + 1)) | (wy >> (cy + 1)) | (wz >> (cz + 1))) & 1u;
+            return wall ? -1 : n + ox[cx + 1] + oy[cy + 1] + oz[cz + 1];
         };
         const S* A = (const S*)a.pdf + sm.off_pdf;
         C h[Q];
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            int64_t idx;
+            int idx;
             if constexpr (PAT == PAT_AA_LOCAL) {
-                idx = (int64_t)i * N + n;
+                idx = i * N + n;
             } else {
-                const int64_t s = nb(-L::cx[i], -L::cy[i], -L::cz[i]);
+                const int s = nb(-L::cx[i], -L::cy[i], -L::cz[i]);
                 if constexpr (PAT == PAT_AB)
-                    idx = s >= 0 ? (int64_t)i * N + s : (int64_t)opp(i) * N + n;
+                    idx = s >= 0 ? i * N + s : opp(i) * N + n;
                 else
-                    idx = s >= 0 ? (int64_t)opp(i) * N + s : (int64_t)i * N + n;
+                    idx = s >= 0 ? opp(i) * N + s : i * N + n;
             }
             h[i] = decode<PREC>(A[idx], L::w[i], a.h16_scale);
         }
@@ -82,14 +92,14 @@ __device__ __forceinline__ void batch_tile(const BatchArgs& a, const BatchSim& s
         S* B = (S*)a.pdf + sm.off_pdf;
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            int64_t idx;
+            int idx;
             if constexpr (PAT == PAT_AB) {
-                idx = (int64_t)i * N + n;  // A/B is not offered for batches; kept for completeness
+                idx = i * N + n;  // A/B is not offered for batches; kept for completeness
             } else if constexpr (PAT == PAT_AA_LOCAL) {
-                idx = (int64_t)opp(i) * N + n;
+                idx = opp(i) * N + n;
             } else {
-                const int64_t d = nb(L::cx[i], L::cy[i], L::cz[i]);
-                idx = d >= 0 ? (int64_t)i * N + d : (int64_t)opp(i) * N + n;
+                const int d = nb(L::cx[i], L::cy[i], L::cz[i]);
+                idx = d >= 0 ? i * N + d : opp(i) * N + n;
             }
             B[idx] = encode<PREC>(h[i], L::w[i], a.h16_inv);
         }
@@ -100,10 +110,23 @@ __device__ __forceinline__ void batch_tile(const BatchArgs& a, const BatchSim& s
                          a.uprev ? a.uprev + sm.off_u : nullptr, n, N);
 }
 
+// Work-item order.  xcd_chunks == 0: block b takes items b, b + G, ...
+// (G = grid size).  xcd_chunks == 1 (G a multiple of 8): the items are cut
+// into 8 contiguous chunks and the blocks b with b mod 8 == j, which the
+// hardware places on one XCD, walk chunk j; neighbouring tiles of a
+// simulation then share that XCD's L2.  Both orders visit every item once.
 template <int LAT, int PREC, int PAT, bool MON>
 __global__ __launch_bounds__(256) void k_batch_step(const BatchArgs a)
 {
-    for (int item = blockIdx.x; item < a.nitems; item += gridDim.x) {
+    int hi = a.nitems, first = blockIdx.x, stride = gridDim.x;
+    if (a.xcd_chunks) {
+        const int chunk = (a.nitems + 7) >> 3;
+        const int lo = (blockIdx.x & 7) * chunk;
+        hi = min(a.nitems, lo + chunk);
+        first = lo + (blockIdx.x >> 3);
+        stride = gridDim.x >> 3;
+    }
+    for (int item = first; item < hi; item += stride) {
         const int sim = __builtin_amdgcn_readfirstlane(a.work[item]);
         const BatchSim& sm = a.sims[sim];
         if (sm.op == OP_PR) batch_tile<LAT, OP_PR, PREC, PAT, MON>(a, sm, item);

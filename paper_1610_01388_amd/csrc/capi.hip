@@ -887,6 +887,8 @@ struct lbm_batch {
     int graph_for_mon = -1;
     int grid = 0;
     int policy = 0;  // tile policy: 0 fewest padded nodes (wide rows on ties), 1 prefer 64-wide rows, 2 fixed 64x4x1
+    int xcd = 1;     // work-item order: 1 = one contiguous chunk per XCD, 0 = plain grid stride
+    size_t bound_total = 0;  // work-buffer bytes the layout had when bound
 };
 
 namespace {
@@ -908,6 +910,18 @@ void tile_for(const lbm_desc& d, int D, int policy, int& tx, int& ty, int& tz)
     }
 }
 
+constexpr int kBatchPolicies = 3;
+
+int64_t tiles_of(const lbm_desc& d, int D, int policy)
+{
+    int tx = 0, ty = 0, tz = 0;
+    tile_for(d, D, policy, tx, ty, tz);
+    return (int64_t)((d.nx + tx - 1) / tx) * ((d.ny + ty - 1) / ty) * ((d.nz + tz - 1) / tz);
+}
+
+// Work list and parameter table for the current tile policy.  The device
+// layout (BatchLayout) is sized for the largest work list any policy gives,
+// so it does not move when the autotuner switches policy.
 int batch_plan(lbm_batch* b)
 {
     b->sims.assign(b->count, BatchSim{});
@@ -940,6 +954,13 @@ int batch_plan(lbm_batch* b)
         s.cf = make_coll<float>(b->r[k]);
     }
     b->nitems = (int)b->work.size();
+    int64_t cap = 0;
+    for (int pol = 0; pol < kBatchPolicies; ++pol) {
+        int64_t items = 0;
+        for (int k = 0; k < b->count; ++k) items += tiles_of(b->d[k], b->D, pol);
+        cap = std::max(cap, items);
+    }
+    if (cap > INT32_MAX) return fail(LBM_EINVAL, "batch too large");
     BatchLayout& L = b->L;
     L.pdf = align_up((size_t)off_pdf * prec_bytes(b->prec));
     bool any_pr = false;
@@ -947,8 +968,8 @@ int batch_plan(lbm_batch* b)
     L.tau = any_pr ? align_up((size_t)off_tau * (b->prec == LBM_FP64 ? 8 : 4)) : 0;
     L.sims = 0;
     L.work_list = align_up(sizeof(BatchSim) * b->count);
-    L.parts = L.work_list + align_up(sizeof(int) * b->nitems);
-    L.recs = L.parts + align_up((size_t)b->nitems * MP_COUNT * sizeof(double));
+    L.parts = L.work_list + align_up(sizeof(int) * (size_t)cap);
+    L.recs = L.parts + align_up((size_t)cap * MP_COUNT * sizeof(double));
     L.counter = L.recs + align_up((size_t)kBatchHistory * b->count * sizeof(MonitorRecord));
     L.uprev = L.counter + kAlign;
     L.stage = L.uprev + align_up((size_t)off_u * sizeof(double));
@@ -957,7 +978,18 @@ int batch_plan(lbm_batch* b)
     size_t stage = std::min(kStageMax, align_up((size_t)maxN * (b->Q + 1) * 8));
     stage = std::max(stage, align_up((size_t)(b->Q + 1) * 8 * 256));
     L.total = L.stage + stage;
+    // the bound buffers were sized for this layout; it must not change
+    if (b->bound && L.total != b->bound_total) return fail(LBM_ESTATE, "batch layout changed after binding");
     return LBM_OK;
+}
+
+// Persistent grid: up to 4096 blocks (16 per CU), a multiple of 8 in the
+// per-XCD order.
+void batch_set_grid(lbm_batch* b)
+{
+    int g = std::max(1, std::min(b->nitems, 4096));
+    if (b->xcd) g = (g + 7) / 8 * 8;
+    b->grid = g;
 }
 
 int batch_need(lbm_batch* b)
@@ -981,6 +1013,7 @@ BatchArgs batch_args(lbm_batch* b)
     a.h16_scale = std::ldexp(1.0f, -b->r[0].fp16_scale_log2);
     a.h16_inv = std::ldexp(1.0f, b->r[0].fp16_scale_log2);
     a.fallback = (b->prec != LBM_FP64 && b->r[0].fp64_fallback) ? 1 : 0;
+    a.xcd_chunks = b->xcd;
     return a;
 }
 
@@ -1079,6 +1112,8 @@ int batch_validate(const lbm_desc* descs, const lbm_rheology* rh, int32_t count)
         if (descs[k].lattice != descs[0].lattice || descs[k].precision != descs[0].precision)
             return fail(LBM_EINVAL, "all simulations of a batch share one lattice and one precision");
         if (descs[k].scheme != LBM_AA) return fail(LBM_EINVAL, "batches use the AA scheme");
+        if ((int64_t)descs[k].nx * descs[k].ny * descs[k].nz * lattice_q(descs[k].lattice) >= ((int64_t)1 << 31))
+            return fail(LBM_EINVAL, "simulation %d: batched simulations need Q * nodes < 2^31", k);
         if (rh[k].fp64_fallback != rh[0].fp64_fallback || rh[k].fp16_scale_log2 != rh[0].fp16_scale_log2)
             return fail(LBM_EINVAL, "all simulations of a batch share the fallback flag and the FP16 scale");
     }
@@ -1143,7 +1178,8 @@ int lbm_batch_bind(lbm_batch* b, void* pdf_dev, void* tau_dev, void* work_dev, v
     b->workbuf = (char*)work_dev;
     b->stream = (hipStream_t)hip_stream;
     b->bound = true;
-    b->grid = std::max(1, std::min(b->nitems, 4096));
+    b->bound_total = b->L.total;
+    batch_set_grid(b);
     batch_drop_graph(b);
     HIPCHK(hipMemcpyAsync(b->workbuf + b->L.sims, b->sims.data(), sizeof(BatchSim) * b->count, hipMemcpyHostToDevice,
                           b->stream));
@@ -1356,6 +1392,31 @@ int lbm_batch_get_tiles(lbm_batch* b, int32_t* tiles)
     return LBM_OK;
 }
 
+int lbm_batch_set_schedule(lbm_batch* b, int32_t tile_policy, int32_t xcd_order)
+{
+    int rc = batch_need(b);
+    if (rc) return rc;
+    if (tile_policy < 0 || tile_policy >= kBatchPolicies || (xcd_order != 0 && xcd_order != 1))
+        return fail(LBM_EINVAL, "tile policy must be 0..%d and the work-item order 0 or 1", kBatchPolicies - 1);
+    HIPCHK(hipStreamSynchronize(b->stream));
+    b->policy = tile_policy;
+    b->xcd = xcd_order;
+    if ((rc = batch_plan(b))) return rc;
+    HIPCHK(hipMemcpy(b->workbuf + b->L.sims, b->sims.data(), sizeof(BatchSim) * b->count, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(b->workbuf + b->L.work_list, b->work.data(), sizeof(int) * b->nitems, hipMemcpyHostToDevice));
+    batch_set_grid(b);
+    batch_drop_graph(b);
+    return LBM_OK;
+}
+
+int lbm_batch_get_schedule(lbm_batch* b, int32_t* tile_policy, int32_t* xcd_order)
+{
+    if (!b || !tile_policy || !xcd_order) return fail(LBM_EINVAL, "NULL argument");
+    *tile_policy = b->policy;
+    *xcd_order = b->xcd;
+    return LBM_OK;
+}
+
 int lbm_batch_autotune(lbm_batch* b, int32_t trial_steps)
 {
     int rc = batch_need(b);
@@ -1366,7 +1427,7 @@ int lbm_batch_autotune(lbm_batch* b, int32_t trial_steps)
     std::vector<char> pdf(b->L.pdf), tau(b->L.tau);
     HIPCHK(hipMemcpy(pdf.data(), b->pdf, b->L.pdf, hipMemcpyDeviceToHost));
     if (b->L.tau) HIPCHK(hipMemcpy(tau.data(), b->tau, b->L.tau, hipMemcpyDeviceToHost));
-    const int parity = b->parity, mon_k = b->mon_k, keep = b->policy;
+    const int parity = b->parity, mon_k = b->mon_k, keep = b->policy + kBatchPolicies * b->xcd;
     const int64_t t = b->t;
     const auto times = b->mon_times;
     b->mon_k = 0;
@@ -1375,12 +1436,14 @@ int lbm_batch_autotune(lbm_batch* b, int32_t trial_steps)
     HIPCHK(hipEventCreate(&e1));
     int best = keep;
     float best_ms = 1e30f;
-    for (int pol = 0; pol < 3 && rc == LBM_OK; ++pol) {
-        b->policy = pol;
+    // candidates: tile policy x work-item order
+    for (int cand = 0; cand < 2 * kBatchPolicies && rc == LBM_OK; ++cand) {
+        b->policy = cand % kBatchPolicies;
+        b->xcd = cand / kBatchPolicies;
         if ((rc = batch_plan(b))) break;
         HIPCHK(hipMemcpy(b->workbuf + b->L.sims, b->sims.data(), sizeof(BatchSim) * b->count, hipMemcpyHostToDevice));
         HIPCHK(hipMemcpy(b->workbuf + b->L.work_list, b->work.data(), sizeof(int) * b->nitems, hipMemcpyHostToDevice));
-        b->grid = std::max(1, std::min(b->nitems, 4096));
+        batch_set_grid(b);
         int par = b->parity;
         int64_t tt = b->t;
         if ((rc = batch_enqueue(b, 2, b->stream, par, tt, false))) break;
@@ -1392,17 +1455,18 @@ int lbm_batch_autotune(lbm_batch* b, int32_t trial_steps)
         HIPCHK(hipEventElapsedTime(&ms, e0, e1));
         if (ms < best_ms) {
             best_ms = ms;
-            best = pol;
+            best = cand;
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    b->policy = best;
+    b->policy = best % kBatchPolicies;
+    b->xcd = best / kBatchPolicies;
     int rc2 = batch_plan(b);
     if (rc2 == LBM_OK) {
         HIPCHK(hipMemcpy(b->workbuf + b->L.sims, b->sims.data(), sizeof(BatchSim) * b->count, hipMemcpyHostToDevice));
         HIPCHK(hipMemcpy(b->workbuf + b->L.work_list, b->work.data(), sizeof(int) * b->nitems, hipMemcpyHostToDevice));
-        b->grid = std::max(1, std::min(b->nitems, 4096));
+        batch_set_grid(b);
     }
     HIPCHK(hipMemcpy(b->pdf, pdf.data(), b->L.pdf, hipMemcpyHostToDevice));
     if (b->L.tau) HIPCHK(hipMemcpy(b->tau, tau.data(), b->L.tau, hipMemcpyHostToDevice));

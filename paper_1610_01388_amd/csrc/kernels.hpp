@@ -124,6 +124,7 @@ struct BatchArgs {
     double* uprev;         // MON: previous-velocity blocks (BatchSim::off_u)
     float h16_scale, h16_inv;
     int fallback;
+    int xcd_chunks;        // work-item order (k_batch_step); needs a grid that is a multiple of 8
 };
 
 hipError_t launch_step(int lat, int op, int prec, int pat, bool mon, int layout, const StepArgs& a, hipStream_t s);

@@ -73,6 +73,7 @@ EXPORTS = ["lbm_last_error", "lbm_lattice_info", "lbm_query_sizes", "lbm_create"
            "lbm_batch_write_populations", "lbm_batch_read_populations", "lbm_batch_read_moments",
            "lbm_batch_set_monitor_interval", "lbm_batch_read_history", "lbm_batch_monitors",
            "lbm_batch_set_graph_steps", "lbm_batch_step", "lbm_batch_time", "lbm_batch_get_tiles",
+           "lbm_batch_get_schedule", "lbm_batch_set_schedule",
            "lbm_batch_autotune", "lbm_batch_destroy"]
 
 _lib = None
@@ -136,6 +137,8 @@ def load_library(path: str = LIB_PATH):
         "lbm_batch_step": ([vp, i64], ctypes.c_int),
         "lbm_batch_time": ([vp, ctypes.POINTER(i64)], ctypes.c_int),
         "lbm_batch_get_tiles": ([vp, i32p], ctypes.c_int),
+        "lbm_batch_get_schedule": ([vp, i32p, i32p], ctypes.c_int),
+        "lbm_batch_set_schedule": ([vp, i32, i32], ctypes.c_int),
         "lbm_batch_autotune": ([vp, i32], ctypes.c_int),
         "lbm_batch_destroy": ([vp], ctypes.c_int),
     }
@@ -496,6 +499,16 @@ def lbm_batch_get_tiles(h, count):
     return t.reshape(count, 3)
 
 
+def lbm_batch_get_schedule(h):
+    p, x = ctypes.c_int32(), ctypes.c_int32()
+    _check(load_library().lbm_batch_get_schedule(h, ctypes.byref(p), ctypes.byref(x)))
+    return p.value, x.value
+
+
+def lbm_batch_set_schedule(h, tile_policy, xcd_order):
+    _check(load_library().lbm_batch_set_schedule(h, int(tile_policy), int(xcd_order)))
+
+
 def lbm_batch_autotune(h, trial_steps=10):
     _check(load_library().lbm_batch_autotune(h, int(trial_steps)))
 
@@ -578,3 +591,10 @@ class Batch:
 
     def autotune(self, trial_steps=10):
         lbm_batch_autotune(self.h, trial_steps)
+
+    def schedule(self):
+        """(tile policy, work-item order) in use."""
+        return lbm_batch_get_schedule(self.h)
+
+    def set_schedule(self, tile_policy, xcd_order):
+        lbm_batch_set_schedule(self.h, tile_policy, xcd_order)

@@ -133,15 +133,42 @@ def test_batch_autotune_keeps_state():
     states = _states(CASES, 90)
     b = _make_batch(CASES, states, graph_steps=10)
     ref = _make_batch(CASES, states, graph_steps=10)
-    b.step(6)
-    ref.step(6)
+    for x in (b, ref):
+        x.set_monitor_interval(5)
+        x.step(6)
     b.autotune(4)
     assert b.time == 6
-    b.step(20)
-    ref.step(20)
+    for x in (b, ref):
+        x.step(20)
     for k in range(len(CASES)):
         assert np.array_equal(b.read_populations(k)[0], ref.read_populations(k)[0])
+    hb, hr = b.history(), ref.history()
+    assert [r[0]["step"] for r in hb] == [0, 5, 10, 15, 20, 25] == [r[0]["step"] for r in hr]
+    assert [[m["residual"] for m in r] for r in hb] == [[m["residual"] for m in r] for r in hr]
     assert b.tiles().shape == (len(CASES), 3) and np.all(np.prod(b.tiles(), axis=1) == 256)
+    assert b.schedule()[0] in (0, 1, 2) and b.schedule()[1] in (0, 1)
+
+
+def test_every_schedule_gives_the_same_state():
+    """Tile policy and work-item order change only the launch geometry."""
+    from paper_1610_01388_amd import lbm
+    states = _states(CASES, 95)
+    ref = None
+    for pol in (0, 1, 2):
+        for order in (0, 1):
+            b = _make_batch(CASES, states, graph_steps=4)
+            b.set_schedule(pol, order)
+            assert b.schedule() == (pol, order)
+            b.step(9)
+            got = [b.read_populations(k)[0] for k in range(len(CASES))]
+            if ref is None:
+                ref = got
+            for g, r in zip(got, ref):
+                assert np.array_equal(g, r), (pol, order)
+            b.close()
+    with pytest.raises(lbm.LbmError):
+        b = _make_batch(CASES, states)
+        b.set_schedule(3, 0)
 
 
 def test_duct_sweep_recipe_runs_fp32():
