@@ -269,6 +269,7 @@ StepArgs step_args(lbm_domain* dm)
     a.wbase = (const uint32_t*)(dm->mask + dm->L.base_off);
     a.W = dm->L.W;
     a.S = dm->S;
+    a.nfluid = dm->Nf;
     a.partials = (double*)dm->work;
     a.uprev = (double*)(dm->work + dm->L.uprev);
     a.N = dm->N;
@@ -339,7 +340,10 @@ int run_steps(lbm_domain* dm, int64_t nsteps)
         HIPCHK(launch_step(dm->d.lattice, dm->r.op, dm->d.precision, pat, mon, dm->d.layout, a, dm->stream));
         if (mon) {
             char* rec = dm->work + dm->L.hist + (size_t)(dm->hist_written % kHistory) * sizeof(MonitorRecord);
-            HIPCHK(launch_finalize((double*)dm->work, a.ntiles, rec, dm->t, (double)dm->N, dm->stream));
+            // the compact AA local phase runs one block per 256 fluid slots, the others one per tile
+            const int64_t nparts = (dm->d.layout == LBM_COMPACT && pat == PAT_AA_LOCAL) ? (dm->Nf + 255) / 256
+                                                                                          : a.ntiles;
+            HIPCHK(launch_finalize((double*)dm->work, nparts, rec, dm->t, (double)dm->N, dm->stream));
             dm->hist_written++;
         }
         if (dm->d.scheme == LBM_AB) dm->cur = 1 - dm->cur;

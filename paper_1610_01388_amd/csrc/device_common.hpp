@@ -31,6 +31,21 @@ __device__ __forceinline__ typename Store<PREC>::S encode(typename Store<PREC>::
     else return h;
 }
 
+// Streaming access to population storage.  Each element is read once and
+// written once per step; with the non-temporal hint on both the loads and
+// the stores, the in-place many-array pattern runs about 5% faster on
+// gfx950 (hint on one side only: no gain).
+template <class S>
+__device__ __forceinline__ S ld_stream(const S* p)
+{
+    return __builtin_nontemporal_load(p);
+}
+template <class S>
+__device__ __forceinline__ void st_stream(S v, S* p)
+{
+    __builtin_nontemporal_store(v, p);
+}
+
 // Wrap a halo coordinate g in [-1, n]: periodic axes wrap, walls give
 // "outside" (treated as solid: halfway bounce-back at the face).
 __device__ __forceinline__ int wrap_halo(int g, int n, int per, bool& out)

@@ -56,6 +56,7 @@ struct StepArgs {
     double* uprev;         // MON: output velocity of the previous fused monitor, [3][S]; overwritten
     int64_t N;             // nodes
     int64_t S;             // direction stride of the population arrays
+    int64_t nfluid;        // fluid nodes (compact: slots 0 .. nfluid-1 are used)
     int W;                 // compact: words per row
     int nx, ny, nz;
     int per[3];

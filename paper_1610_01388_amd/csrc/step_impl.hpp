@@ -240,12 +240,18 @@ __global__ __launch_bounds__(256) void k_step_compact(const StepArgs a, const ui
     const bool wave_in = (y < a.ny) && (z < a.nz);
     const int64_t St = a.S;
 
-    // neighbourhood: fluid flag (bit d) and compact index of node x + d,
-    // d = (dx, dy, dz) in {-1,0,1}^3, index (dx+1) + 3 (dy+1) + 9 (dz+1)
+    // Neighbourhood of node x: fluid flag of x + d (bit d of nbf, d = (dx, dy,
+    // dz) in {-1,0,1}^3, index (dx+1) + 3 (dy+1) + 9 (dz+1)); for each of the
+    // rows r = (dy+1) + 3 (dz+1), the compact index im[r] at x in that row (x
+    // itself if fluid, else the next fluid node), and the wave-uniform indices
+    // li[r] / ri[r] of the left neighbour of lane 0 and of the right
+    // neighbour of the segment's last lane.  Within the segment the x-1 and
+    // x+1 neighbours are im - 1 and im + [x fluid].
     uint32_t nbf = 0;
-    uint32_t nbi[27];
+    uint32_t im[9], li[9], ri[9];
 #pragma unroll
-    for (int k = 0; k < 27; ++k) nbi[k] = 0;
+    for (int r = 0; r < 9; ++r) im[r] = li[r] = ri[r] = 0;
+    const bool last = (lane == 63) || (x == a.nx - 1);
 #pragma unroll
     for (int dz = -1; dz <= 1; ++dz) {
         if (D == 2 && dz != 0) continue;
@@ -261,8 +267,8 @@ __global__ __launch_bounds__(256) void k_step_compact(const StepArgs a, const ui
                 if (a.per[2]) zz = (zz + a.nz) % a.nz;
                 else rv = false;
             }
-            uint64_t mb = 0, lb = 0, rb = 0;
-            uint32_t mbase = 0, li = 0, ri = 0;
+            uint64_t mb = 0;
+            uint32_t mbase = 0, lidx = 0, ridx = 0;
             bool lf = false, rf = false;
             if (rv) {
                 const int64_t row = ((int64_t)yy + (int64_t)a.ny * zz) * a.W;
@@ -272,44 +278,41 @@ __global__ __launch_bounds__(256) void k_step_compact(const StepArgs a, const ui
                 if (x0 > 0) wl = ttx - 1;
                 else if (a.per[0]) { wl = (a.nx - 1) >> 6; bl = (a.nx - 1) & 63; }
                 if (wl >= 0) {
-                    lb = bits[row + wl];
+                    const uint64_t lb = bits[row + wl];
                     lf = (lb >> bl) & 1;
-                    li = wbase[row + wl] + (uint32_t)__popcll(lb & ((1ull << bl) - 1ull));
+                    lidx = wbase[row + wl] + (uint32_t)__popcll(lb & ((1ull << bl) - 1ull));
                 }
                 int wr = -1;
                 if (x0 + 64 < a.nx) wr = ttx + 1;
                 else if (a.per[0]) wr = 0;
                 if (wr >= 0) {
-                    rb = bits[row + wr];
-                    rf = rb & 1;
-                    ri = wbase[row + wr];
+                    rf = bits[row + wr] & 1;
+                    ridx = wbase[row + wr];
                 }
             }
             const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(mb >> 32),
                                                             __builtin_amdgcn_mbcnt_lo((uint32_t)mb, 0u));
             const bool fm = (mb >> lane) & 1;
-            const uint32_t im = mbase + rank;
-            bool fL;
-            uint32_t iL;
-            if (lane > 0) { fL = (mb >> (lane - 1)) & 1; iL = im - 1; }
-            else { fL = lf; iL = li; }
-            const bool last = (lane == 63) || (x == a.nx - 1);
-            bool fR;
-            uint32_t iR;
-            if (!last) { fR = (mb >> (lane + 1)) & 1; iR = im + (fm ? 1u : 0u); }
-            else { fR = rf; iR = ri; }
-            const int base = 3 * (dy + 1) + 9 * (dz + 1);
-            nbf |= (fL ? 1u : 0u) << (base + 0);
-            nbf |= (fm ? 1u : 0u) << (base + 1);
-            nbf |= (fR ? 1u : 0u) << (base + 2);
-            nbi[base + 0] = iL;
-            nbi[base + 1] = im;
-            nbi[base + 2] = iR;
+            const bool fL = lane > 0 ? ((mb >> (lane - 1)) & 1) : lf;
+            const bool fR = !last ? ((mb >> (lane + 1)) & 1) : rf;
+            const int r = (dy + 1) + 3 * (dz + 1);
+            nbf |= (fL ? 1u : 0u) << (3 * r + 0);
+            nbf |= (fm ? 1u : 0u) << (3 * r + 1);
+            nbf |= (fR ? 1u : 0u) << (3 * r + 2);
+            im[r] = mbase + rank;
+            li[r] = lidx;
+            ri[r] = ridx;
         }
     }
+    // compact index of the neighbour x + (dx, row r) (valid when it is fluid)
+    auto nbi = [&](int dx, int r) -> uint32_t {
+        if (dx == 0) return im[r];
+        if (dx < 0) return lane > 0 ? im[r] - 1u : li[r];
+        return !last ? im[r] + ((nbf >> (3 * r + 1)) & 1u) : ri[r];
+    };
     constexpr int SELF = 13;
     const bool active = wave_in && ((nbf >> SELF) & 1);
-    const int64_t k = nbi[SELF];
+    const int64_t k = im[4];
 
     C h[Q];
     C tau_prev = C(0);
@@ -325,12 +328,12 @@ __global__ __launch_bounds__(256) void k_step_compact(const StepArgs a, const ui
             if constexpr (PAT == PAT_AA_LOCAL) {
                 idx = (int64_t)i * St + k;
             } else {
-                const int d = (1 - L::cx[i]) + 3 * (1 - L::cy[i]) + 9 * (1 - L::cz[i]);  // x - c_i
-                const bool fl = (nbf >> d) & 1;
+                const int r = (1 - L::cy[i]) + 3 * (1 - L::cz[i]);  // row of x - c_i
+                const bool fl = (nbf >> (3 * r + 1 - L::cx[i])) & 1;
                 if constexpr (PAT == PAT_AB)
-                    idx = fl ? (int64_t)i * St + nbi[d] : (int64_t)opp(i) * St + k;
+                    idx = fl ? (int64_t)i * St + nbi(-L::cx[i], r) : (int64_t)opp(i) * St + k;
                 else
-                    idx = fl ? (int64_t)opp(i) * St + nbi[d] : (int64_t)i * St + k;
+                    idx = fl ? (int64_t)opp(i) * St + nbi(-L::cx[i], r) : (int64_t)i * St + k;
             }
             h[i] = decode<PREC>(A[idx], L::w[i], a.h16_scale);
         }
@@ -338,6 +341,15 @@ __global__ __launch_bounds__(256) void k_step_compact(const StepArgs a, const ui
 
         collide_node<LAT, OP, PREC>(h, tau_prev, a.fallback, a.cd, cp, mo, pr, used_fb);
 
+        if constexpr (PAT == PAT_AA_PULL) {
+            // Rebuild the neighbour indices for the stores from im, nbf and the
+            // wave-uniform edges instead of keeping the 27 load-side values
+            // alive through the collision (register pressure sets the
+            // occupancy of this kernel).  The empty asm only hides the values'
+            // history from the optimiser; it emits no instruction.
+#pragma unroll
+            for (int r = 0; r < 9; ++r) asm volatile("" : "+v"(im[r]));
+        }
         S* B = (S*)a.dst;
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
@@ -347,9 +359,9 @@ __global__ __launch_bounds__(256) void k_step_compact(const StepArgs a, const ui
             } else if constexpr (PAT == PAT_AA_LOCAL) {
                 idx = (int64_t)opp(i) * St + k;
             } else {
-                const int d = (1 + L::cx[i]) + 3 * (1 + L::cy[i]) + 9 * (1 + L::cz[i]);  // x + c_i
-                const bool fl = (nbf >> d) & 1;
-                idx = fl ? (int64_t)i * St + nbi[d] : (int64_t)opp(i) * St + k;
+                const int r = (1 + L::cy[i]) + 3 * (1 + L::cz[i]);  // row of x + c_i
+                const bool fl = (nbf >> (3 * r + 1 + L::cx[i])) & 1;
+                idx = fl ? (int64_t)i * St + nbi(L::cx[i], r) : (int64_t)opp(i) * St + k;
             }
             B[idx] = encode<PREC>(h[i], L::w[i], a.h16_inv);
         }
@@ -359,12 +371,55 @@ __global__ __launch_bounds__(256) void k_step_compact(const StepArgs a, const ui
         monitor_block<C>(active, mo, pr, cp, used_fb, a.partials + (int64_t)tile * MP_COUNT, a.uprev, k, St);
 }
 
+// Compact layout, AA local phase: every fluid node's streamed populations
+// already sit in its own slots, so this half of the AA pair needs no
+// geometry at all.  One thread per fluid slot, 256 slots per block: every
+// lane is busy and each direction is one contiguous run per wavefront.
+// Monitor partials: one per block.
+template <int LAT, int OP, int PREC, bool MON>
+__global__ __launch_bounds__(256) void k_local_slots(const StepArgs a)
+{
+    using L = Lattice<LAT>;
+    constexpr int Q = L::Q;
+    using S = typename Store<PREC>::S;
+    using C = typename Store<PREC>::C;
+    using T = typename Store<PREC>::T;
+
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const bool active = k < a.nfluid;
+    const int64_t St = a.S;
+    const Coll<C>& cp = coll_of<C>(a);
+    Moments<C> mo;
+    Pre<C> pr;
+    bool used_fb = false;
+    if (active) {
+        const S* A = (const S*)a.src;
+        C h[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) h[i] = decode<PREC>(ld_stream(A + (int64_t)i * St + k), L::w[i], a.h16_scale);
+        C tau_prev = C(0);
+        if constexpr (OP == OP_PR) tau_prev = (C)((const T*)a.tau)[k];
+
+        collide_node<LAT, OP, PREC>(h, tau_prev, a.fallback, a.cd, cp, mo, pr, used_fb);
+
+        S* B = (S*)a.dst;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) st_stream(encode<PREC>(h[i], L::w[i], a.h16_inv), B + (int64_t)opp(i) * St + k);
+        if constexpr (OP == OP_PR) ((T*)a.tau)[k] = (T)pr.tau_p;
+    }
+    if constexpr (MON)
+        monitor_block<C>(active, mo, pr, cp, used_fb, a.partials + (int64_t)blockIdx.x * MP_COUNT, a.uprev, k, St);
+}
+
 template <int LAT, int OP, int PREC, int PAT, bool MON>
 static hipError_t go_step(int layout, const StepArgs& a, hipStream_t s)
 {
     const int threads = a.tx * a.ty * a.tz;
     const dim3 grid(8 * a.tiles_per_xcd);
-    if (layout == LAYOUT_COMPACT) {
+    if (layout == LAYOUT_COMPACT && PAT == PAT_AA_LOCAL) {
+        const int64_t blocks = (a.nfluid + 255) / 256;
+        if (blocks > 0) hipLaunchKernelGGL((k_local_slots<LAT, OP, PREC, MON>), dim3((unsigned)blocks), dim3(256), 0, s, a);
+    } else if (layout == LAYOUT_COMPACT) {
         hipLaunchKernelGGL((k_step_compact<LAT, OP, PREC, PAT, MON>), grid, dim3(threads), 0, s, a, a.bits, a.wbase);
     } else {
         const int hz = (Lattice<LAT>::D == 3) ? a.tz + 2 : 1;

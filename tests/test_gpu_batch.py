@@ -144,7 +144,10 @@ def test_batch_autotune_keeps_state():
         assert np.array_equal(b.read_populations(k)[0], ref.read_populations(k)[0])
     hb, hr = b.history(), ref.history()
     assert [r[0]["step"] for r in hb] == [0, 5, 10, 15, 20, 25] == [r[0]["step"] for r in hr]
-    assert [[m["residual"] for m in r] for r in hb] == [[m["residual"] for m in r] for r in hr]
+    # monitors are sums over work items: another tile policy sums in another order
+    for rb, rr in zip(hb, hr):
+        for mb, mr in zip(rb, rr):
+            assert abs(mb["residual"] - mr["residual"]) <= 1e-12 * mr["residual"]
     assert b.tiles().shape == (len(CASES), 3) and np.all(np.prod(b.tiles(), axis=1) == 256)
     assert b.schedule()[0] in (0, 1, 2) and b.schedule()[1] in (0, 1)
 
