@@ -303,8 +303,9 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "algorithmic_bytes_per_launch": per_launch, "bytes_per_fluid_node": bpn,
-                     "kernel": f"k_step{'_compact' if args.layout == 'COMPACT' else ''}<D3Q27, IR, FP64, "
-                               "AA pull/local> (mean of the two alternating AA phases)",
+                     "kernel": ("k_step_compact<D3Q27, IR, FP64, AA pull> and k_local_slots<D3Q27, IR, FP64> "
+                                "(AA local)" if args.layout == "COMPACT" else "k_step<D3Q27, IR, FP64, AA pull/local>")
+                               + ", mean of the two alternating AA phases",
                      "kernel_source_hash": khash},
     }
     if hist:

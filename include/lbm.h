@@ -206,6 +206,16 @@ int lbm_load(lbm_domain* dom, const void* blob, size_t bytes);
  * compact layout needs tx == 64 (one wavefront per 64-node row segment). */
 int lbm_set_tile(lbm_domain* dom, int32_t tx, int32_t ty, int32_t tz);
 int lbm_get_tile(lbm_domain* dom, int32_t* tx, int32_t* ty, int32_t* tz);
+/* Order in which the step walks its tiles: bricks of whole rows x
+ * brick_rows tile rows x brick_planes tile planes (x fastest, then y, then
+ * z inside a brick), so that tiles that touch the same cache lines across
+ * z run close together and on one XCD.  0 selects the default (compact
+ * layout: about 16 tiles per brick plane and one slab of planes per XCD;
+ * dense layout: one brick, i.e. plain x, y, z order); values are clamped to
+ * the tile grid.  The order changes timing only, never results.  The getter
+ * reports the values in effect. */
+int lbm_set_tile_order(lbm_domain* dom, int32_t brick_rows, int32_t brick_planes);
+int lbm_get_tile_order(lbm_domain* dom, int32_t* brick_rows, int32_t* brick_planes);
 /* Time candidate tile shapes on the bound buffers (the state is saved and
  * restored around the trial steps) and keep the fastest; synchronises. */
 int lbm_autotune(lbm_domain* dom, int32_t trial_steps);

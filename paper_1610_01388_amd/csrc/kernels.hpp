@@ -64,6 +64,8 @@ struct StepArgs {
     int ntx, nty, ntz;     // tiles per axis
     int ntiles;
     int tiles_per_xcd;     // ceil(ntiles / 8): tiles handed to each XCD as one contiguous range
+    int bry, brz;          // tile order: bricks of whole rows x bry row-blocks x brz planes
+    int stream_hint;       // non-temporal access where the kernel supports it (state larger than the caches)
     int fallback;          // reduced precision: FP64 redo of near-yield nodes
     float h16_scale;       // FP16: 2^-k  (h = half * w * 2^-k)
     float h16_inv;         // FP16: 2^k

@@ -48,6 +48,31 @@ __device__ __forceinline__ void collide_node(typename Store<PREC>::C (&h)[Lattic
     relax<LAT, OP>(h, mo, pr, cp);
 }
 
+// Tile coordinates of the t-th tile in processing order.  Tiles are walked
+// in bricks of whole rows (all x tiles) x bry row-blocks x brz planes, x
+// fastest, then y, then z inside a brick, bricks y-major inside a z-slab of
+// brz planes.  Neighbours in z are then ntx * bry tiles apart in the order,
+// so a cache line that two z-adjacent tiles both touch (bounce-back reads
+// and writes land in the node's own slots, which the wave of the next plane
+// also streams) is still in the L2 the second time.  With one z-slab per
+// XCD-contiguous range of tiles, the slab's neighbours stay on one XCD.  A
+// bijection of [0, ntiles) for any bry in [1, nty], brz in [1, ntz].
+__device__ __forceinline__ void tile_coords(const StepArgs& a, int t, int& ttx, int& tty, int& ttz)
+{
+    const int per_zb = a.ntx * a.nty * a.brz;
+    const int zb = t / per_zb;
+    const int u = t - zb * per_zb;
+    const int bz = min(a.brz, a.ntz - zb * a.brz);
+    const int per_yb = a.ntx * a.bry * bz;
+    const int yb = u / per_yb;
+    const int v = u - yb * per_yb;
+    const int by = min(a.bry, a.nty - yb * a.bry);
+    ttx = v % a.ntx;
+    const int r = v / a.ntx;
+    tty = yb * a.bry + r % by;
+    ttz = zb * a.brz + r / by;
+}
+
 // Per-block monitor partial sums of the state the step started from.  With
 // uprev set, the node's output velocity is compared with the one stored at
 // the previous fused monitor (slot idx, components stride apart) and then
@@ -106,10 +131,8 @@ __global__ __launch_bounds__(256) void k_step(const StepArgs a)
     const int lyz = t / a.tx;
     const int ly = lyz % a.ty;
     const int lz = lyz / a.ty;
-    const int ttx = tile % a.ntx;
-    const int trem = tile / a.ntx;
-    const int tty = trem % a.nty;
-    const int ttz = trem / a.nty;
+    int ttx, tty, ttz;
+    tile_coords(a, tile, ttx, tty, ttz);
     const int x = ttx * a.tx + lx;
     const int y = tty * a.ty + ly;
     const int z = ttz * a.tz + lz;
@@ -229,10 +252,8 @@ __global__ __launch_bounds__(256) void k_step_compact(const StepArgs a, const ui
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int ly = wv % a.ty;
     const int lz = wv / a.ty;
-    const int ttx = tile % a.ntx;
-    const int trem = tile / a.ntx;
-    const int tty = trem % a.nty;
-    const int ttz = trem / a.nty;
+    int ttx, tty, ttz;
+    tile_coords(a, tile, ttx, tty, ttz);
     const int x0 = ttx * 64;
     const int x = x0 + lane;
     const int y = tty * a.ty + ly;
@@ -375,8 +396,10 @@ __global__ __launch_bounds__(256) void k_step_compact(const StepArgs a, const ui
 // already sit in its own slots, so this half of the AA pair needs no
 // geometry at all.  One thread per fluid slot, 256 slots per block: every
 // lane is busy and each direction is one contiguous run per wavefront.
-// Monitor partials: one per block.
-template <int LAT, int OP, int PREC, bool MON>
+// NT: non-temporal loads and stores, for states larger than the caches
+// (a cache-resident state would only lose its hits).  Monitor partials: one
+// per block.
+template <int LAT, int OP, int PREC, bool MON, bool NT>
 __global__ __launch_bounds__(256) void k_local_slots(const StepArgs a)
 {
     using L = Lattice<LAT>;
@@ -396,7 +419,10 @@ __global__ __launch_bounds__(256) void k_local_slots(const StepArgs a)
         const S* A = (const S*)a.src;
         C h[Q];
 #pragma unroll
-        for (int i = 0; i < Q; ++i) h[i] = decode<PREC>(ld_stream(A + (int64_t)i * St + k), L::w[i], a.h16_scale);
+        for (int i = 0; i < Q; ++i) {
+            const S* p = A + (int64_t)i * St + k;
+            h[i] = decode<PREC>(NT ? ld_stream(p) : *p, L::w[i], a.h16_scale);
+        }
         C tau_prev = C(0);
         if constexpr (OP == OP_PR) tau_prev = (C)((const T*)a.tau)[k];
 
@@ -404,7 +430,12 @@ __global__ __launch_bounds__(256) void k_local_slots(const StepArgs a)
 
         S* B = (S*)a.dst;
 #pragma unroll
-        for (int i = 0; i < Q; ++i) st_stream(encode<PREC>(h[i], L::w[i], a.h16_inv), B + (int64_t)opp(i) * St + k);
+        for (int i = 0; i < Q; ++i) {
+            S* p = B + (int64_t)opp(i) * St + k;
+            const S v = encode<PREC>(h[i], L::w[i], a.h16_inv);
+            if constexpr (NT) st_stream(v, p);
+            else *p = v;
+        }
         if constexpr (OP == OP_PR) ((T*)a.tau)[k] = (T)pr.tau_p;
     }
     if constexpr (MON)
@@ -418,7 +449,12 @@ static hipError_t go_step(int layout, const StepArgs& a, hipStream_t s)
     const dim3 grid(8 * a.tiles_per_xcd);
     if (layout == LAYOUT_COMPACT && PAT == PAT_AA_LOCAL) {
         const int64_t blocks = (a.nfluid + 255) / 256;
-        if (blocks > 0) hipLaunchKernelGGL((k_local_slots<LAT, OP, PREC, MON>), dim3((unsigned)blocks), dim3(256), 0, s, a);
+        if (blocks > 0) {
+            if (a.stream_hint)
+                hipLaunchKernelGGL((k_local_slots<LAT, OP, PREC, MON, true>), dim3((unsigned)blocks), dim3(256), 0, s, a);
+            else
+                hipLaunchKernelGGL((k_local_slots<LAT, OP, PREC, MON, false>), dim3((unsigned)blocks), dim3(256), 0, s, a);
+        }
     } else if (layout == LAYOUT_COMPACT) {
         hipLaunchKernelGGL((k_step_compact<LAT, OP, PREC, PAT, MON>), grid, dim3(threads), 0, s, a, a.bits, a.wbase);
     } else {

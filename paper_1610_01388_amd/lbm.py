@@ -68,7 +68,7 @@ EXPORTS = ["lbm_last_error", "lbm_lattice_info", "lbm_query_sizes", "lbm_create"
            "lbm_set_mask", "lbm_init_equilibrium", "lbm_write_populations", "lbm_read_populations",
            "lbm_step", "lbm_time", "lbm_set_monitor_interval", "lbm_read_history", "lbm_monitors",
            "lbm_set_umax_limit", "lbm_read_moments", "lbm_save", "lbm_load", "lbm_set_tile",
-           "lbm_get_tile", "lbm_autotune", "lbm_destroy",
+           "lbm_get_tile", "lbm_set_tile_order", "lbm_get_tile_order", "lbm_autotune", "lbm_destroy",
            "lbm_batch_query_sizes", "lbm_batch_create", "lbm_batch_bind", "lbm_batch_init_equilibrium",
            "lbm_batch_write_populations", "lbm_batch_read_populations", "lbm_batch_read_moments",
            "lbm_batch_set_monitor_interval", "lbm_batch_read_history", "lbm_batch_monitors",
@@ -119,6 +119,8 @@ def load_library(path: str = LIB_PATH):
         "lbm_load": ([vp, vp, ctypes.c_size_t], ctypes.c_int),
         "lbm_set_tile": ([vp, i32, i32, i32], ctypes.c_int),
         "lbm_get_tile": ([vp, i32p, i32p, i32p], ctypes.c_int),
+        "lbm_set_tile_order": ([vp, i32, i32], ctypes.c_int),
+        "lbm_get_tile_order": ([vp, i32p, i32p], ctypes.c_int),
         "lbm_autotune": ([vp, i32], ctypes.c_int),
         "lbm_destroy": ([vp], ctypes.c_int),
         "lbm_batch_query_sizes": ([ctypes.POINTER(lbm_desc), ctypes.POINTER(lbm_rheology), i32,
@@ -282,6 +284,16 @@ def lbm_get_tile(h):
     return tuple(x.value for x in v)
 
 
+def lbm_set_tile_order(h, brick_rows, brick_planes):
+    _check(load_library().lbm_set_tile_order(h, int(brick_rows), int(brick_planes)))
+
+
+def lbm_get_tile_order(h):
+    r, p = ctypes.c_int32(), ctypes.c_int32()
+    _check(load_library().lbm_get_tile_order(h, ctypes.byref(r), ctypes.byref(p)))
+    return r.value, p.value
+
+
 def lbm_autotune(h, trial_steps=10):
     _check(load_library().lbm_autotune(h, int(trial_steps)))
 
@@ -402,6 +414,12 @@ class Domain:
 
     def tile(self):
         return lbm_get_tile(self.h)
+
+    def set_tile_order(self, brick_rows=0, brick_planes=0):
+        lbm_set_tile_order(self.h, brick_rows, brick_planes)
+
+    def tile_order(self):
+        return lbm_get_tile_order(self.h)
 
     def autotune(self, trial_steps=10):
         lbm_autotune(self.h, trial_steps)
