@@ -10,7 +10,9 @@ value = fluid-node updates per second (MLUPS) over the timed steps.
 Also reported ("forms"): the PR operator, FP32 and FP16 storage (the FP16
 form on the 384^3 pack, seed 2, with the FP64 fallback near the yield
 surface), the 4x128x128 D3Q19 duct, and the batched duct sweep, each with
-its velocity/flux/plug-volume error against an FP64 run of the same input.
+its velocity/flux/plug-volume error against an FP64 run of the same input;
+and the creeping-flow cylinder cell of the paper's Table 2 run to steady
+state, with its similarity numbers against the printed ones.
 
 Roofline: algorithmic bytes of the step kernel per launch (fluid nodes x
 2 Q x 8 B, plus 16 B per fluid node of relaxation time for PR) over its
@@ -187,6 +189,38 @@ def batch_form(torch, lbm, cases, warmup, steps, graph_steps=1000):
             "error_vs_fp64": err}
 
 
+def cylinder_form(torch, lbm, inputs):
+    """Validation form: the creeping-flow cylinder cell of Table 2 (IR,
+    sigma_y = 1e-5), from rest to steady state; MLUPS of the whole run and
+    the similarity numbers against the printed ones (U = mean over fluid
+    nodes)."""
+    case = inputs.cylinder_case("IR", sigma_y=1e-5)
+    dom = lbm.Domain(case["lattice"], case["dims"], case["periodic"], "IR", case["nu_p"], case["sigma_y"],
+                     g=case["g"])
+    dom.set_mask(case["mask"])
+    fluid = int((case["mask"] == 0).sum())
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    prev, n = None, 0
+    while n < 1_000_000:
+        dom.step(2000)
+        n += 2000
+        U = dom.monitors()["flux"][0]
+        if prev is not None and abs(U - prev) <= 1e-9 * abs(U):
+            break
+        prev = U
+    dt = time.perf_counter() - t0
+    dom.close()
+    U /= 1.0 - case["mask"].mean()
+    D, nu, g, sy = case["D"], case["nu_p"], case["g"][0], case["sigma_y"]
+    got = {"Re": U * D / nu, "Bn": sy * D / (nu * U), "f": 2 * D * g / U ** 2}
+    want = {"Re": 0.802, "Bn": 1.994, "f": 19.890}  # Sec. 4.5.2, Table 2, IR row sigma_y = 1e-5 (read x10)
+    return {"form": "cylinder cell 80x80 D2Q9 IR (Table 2 row 2), rest to steady state", "lattice": "D2Q9",
+            "precision": "FP64", "fluid_nodes": fluid, "steps": n, "seconds": dt,
+            "MLUPS": fluid * n / dt / 1e6, "similarity": got, "paper": want,
+            "rel_error": {k: abs(got[k] - want[k]) / want[k] for k in want}}
+
+
 def cpu_baseline(case, mask, fluid):
     """The FP64 oracle (single thread, as it stands) on one step of the
     same workload."""
@@ -350,6 +384,8 @@ def main():
         forms += [d64, d32]
         log("forms: batched sweep, 256 D3Q19 ducts (sides 32..160, length 4), FP32 vs FP64, 1000-step graph")
         forms.append(batch_form(torch, lbm, inputs.batch_sweep(), 1000, 1000))
+        log("forms: cylinder-array validation cell (Table 2), rest to steady state")
+        forms.append(cylinder_form(torch, lbm, inputs))
     result["forms"] = forms
 
     if not args.no_cpu:

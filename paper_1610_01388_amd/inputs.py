@@ -178,6 +178,17 @@ def porous_case(op: str, n: int = 256, Bi: float = 1.0, nu_p: float = 0.1, g: fl
                 sigma_y=Bi * g * 2.0 * radius / 4.0, m=m, g=(g, 0.0, 0.0))
 
 
+def cylinder_case(op: str, L: int = 80, D: float = 32.0, nu_p: float = 0.08, g: float = 1.25e-6,
+                  sigma_y: float = 0.0, m: float = 1e7):
+    """Periodic array of circular cylinders (Sec. 4.5): one cylinder of
+    diameter D centred in an L x L periodic D2Q9 cell, body force along x.
+    Defaults: the creeping-flow cell (D = 0.4 L, nu_p = 0.08, g = 1.25e-6).
+    PR's Papanastasiou parameter is not printed for these runs; m = 1e7
+    makes m sigma_y / rho large against nu_p for every yield stress used."""
+    return dict(lattice="D2Q9", dims=(L, L, 1), periodic=(1, 1, 1), op=op, nu_p=nu_p, sigma_y=sigma_y,
+                m=m if op == "PR" else 0.0, g=(g, 0.0, 0.0), mask=cylinder_array_mask(L, D), D=D)
+
+
 def batch_sweep(count: int = 256, seed: int = 3, smin: int = 32, smax: int = 160,
                 length: int = 4, nu_p: float = 0.1, bi_max: float = 10.0):
     """Independent square ducts of uneven section.  For each k: side s_k
