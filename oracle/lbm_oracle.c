@@ -176,6 +176,11 @@ static void collide_pr(const lattice_t* L, const orc_rheology* rh, const double*
     for (int a = 0; a < 3; ++a)
         for (int b = 0; b < 3; ++b) D[a][b] = -Pneq[a][b] / (2.0 * rho * CS2 * tau_prev);
 
+    /* Sec. 4.2.2: for a flow known to run along one axis, the normal
+     * component of the strain rate along it (a Burnett-order artefact of the
+     * kinetic stress) can be set to zero. */
+    if (rh->flow_axis >= 1 && rh->flow_axis <= 3) D[rh->flow_axis - 1][rh->flow_axis - 1] = 0.0;
+
     /* Characteristic strain rate (Sec. 1, Eq. 4), full tensor. */
     double DD = 0.0;
     for (int a = 0; a < 3; ++a)
@@ -248,6 +253,11 @@ static void collide_ir(const lattice_t* L, const orc_rheology* rh, const double*
 
     /* T = sum c c (fbar - f_eq) (Sec. 2.3, below Eq. 31). */
     second_moment_of_difference(L, fbar, feq_back, T);
+
+    /* Sec. 4.2.2: with the flow direction known, T's normal component along
+     * it is set to zero before the deviator, so it is not redistributed to
+     * the transverse directions. */
+    if (rh->flow_axis >= 1 && rh->flow_axis <= 3) T[rh->flow_axis - 1][rh->flow_axis - 1] = 0.0;
 
     /* Reading: only the deviatoric part enters (text below Eq. 29); the
      * printed sigma - Tr(sigma) I is read as sigma - Tr(sigma)/d I, applied

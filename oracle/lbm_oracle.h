@@ -34,7 +34,10 @@ enum { ORC_PR = 0, ORC_IR = 1, ORC_BGK = 2 };
  * tau = 1/2 + 3 nu_p). */
 typedef struct {
     int32_t op;
-    int32_t pad_;
+    int32_t flow_axis; /* 0: off; 1, 2, 3: the flow is known to be along x, y,
+                          z and the axis-normal component is dropped from the
+                          collision (Sec. 4.2.2): PR's strain rate loses d_aa,
+                          IR's T loses T_aa before the deviator */
     double nu_p;      /* plastic (kinematic) viscosity, lattice units      */
     double sigma_y;   /* yield stress (per unit density), lattice units    */
     double m;         /* Papanastasiou regularisation parameter  (PR)      */

@@ -39,10 +39,14 @@ MUTATIONS = {
                                "Tdev[a][b] = T[a][b];"),
     "residual_reference_not_kept": ("    if (record)\n        for (int64_t j = 0;", "    if (0)\n        for (int64_t j = 0;"),
     "residual_unsquared": ("        num += d2;", "        num += sqrt(d2);"),
+    "flow_axis_off_by_one": ("if (rh->flow_axis >= 1 && rh->flow_axis <= 3) T[rh->flow_axis - 1][rh->flow_axis - 1] = 0.0;",
+                             "if (rh->flow_axis >= 1 && rh->flow_axis <= 3) T[rh->flow_axis % 3][rh->flow_axis % 3] = 0.0;"),
+    "flow_axis_pr_ignored": ("if (rh->flow_axis >= 1 && rh->flow_axis <= 3) D[rh->flow_axis - 1][rh->flow_axis - 1] = 0.0;",
+                             "if (0) D[rh->flow_axis - 1][rh->flow_axis - 1] = 0.0;"),
 }
 
 PIN_TESTS = ["tests/test_oracle_lattice.py", "tests/test_oracle_operators.py",
-             "tests/test_oracle_flows.py", "tests/test_oracle_residual.py"]
+             "tests/test_oracle_flows.py", "tests/test_oracle_residual.py", "tests/test_oracle_burnett.py"]
 
 
 @pytest.mark.parametrize("name", sorted(MUTATIONS))
