@@ -93,7 +93,11 @@ typedef struct {
     double fallback_band;    /* IR: |T/(sqrt2 sigma_y) - 1| < band; PR:
                                 m*gamma_dot < band -> node done in FP64      */
     int32_t fp16_scale_log2; /* FP16: k in h*2^k/w (0..24), e.g. 14           */
-    int32_t reserved;
+    int32_t flow_axis;       /* 0: off.  1, 2, 3: the flow is known to run along
+                                x, y, z; the collision then drops that axis's
+                                normal component (Sec. 4.2.2): PR leaves d_aa
+                                out of the strain rate, IR sets T_aa to zero
+                                before the deviator.  Other values: EINVAL. */
 } lbm_rheology;
 
 typedef struct {

@@ -102,6 +102,7 @@ int check_rheology(const lbm_rheology* r)
     }
     if (r->fp16_scale_log2 < 0 || r->fp16_scale_log2 > 24) return fail(LBM_EINVAL, "fp16_scale_log2 outside 0..24");
     if (!(r->fallback_band >= 0)) return fail(LBM_EINVAL, "fallback_band must be >= 0");
+    if (r->flow_axis < 0 || r->flow_axis > 3) return fail(LBM_EINVAL, "flow_axis must be 0 (off) or 1..3");
     return LBM_OK;
 }
 
@@ -222,6 +223,7 @@ Coll<C> make_coll(const lbm_rheology& r)
     const double gc = r.gamma_c > 0 ? r.gamma_c : 1e-8;
     c.pr_ec = (C)(-std::expm1(-r.m * gc) / gc);
     c.band = (C)r.fallback_band;
+    c.axis = r.flow_axis;
     return c;
 }
 

@@ -29,6 +29,7 @@ template <class C> struct Coll {
                   // ir_b = 2 sqrt2 sigma_y/(1+6nu_p)  (Eqs. 39-40 combined)
     C pr_ec;      // PR: -expm1(-m gamma_c) / gamma_c  (nu_app at the cut-off is nu_p + sigma_y pr_ec / rho)
     C band;       // FP64 fallback band
+    int axis;     // 0, or 1..3: known flow axis whose normal component the collision drops (Sec. 4.2.2)
 };
 
 template <class C> struct Moments {
@@ -125,6 +126,10 @@ __device__ __forceinline__ Pre<C> rheology(const Moments<C>& mo, const Coll<C>& 
         C dd[6];
 #pragma unroll
         for (int a = 0; a < 6; ++a) dd[a] = coef * t[a];
+        // known flow axis: its normal strain rate is a Burnett-order artefact
+        if (p.axis == 1) dd[0] = C(0);
+        if (p.axis == 2) dd[1] = C(0);
+        if (p.axis == 3) dd[2] = C(0);
         const C gamma = d_sqrt(C(2) * frob2(dd));
         C nu;
         if (gamma >= p.gamma_c) {
@@ -146,6 +151,10 @@ __device__ __forceinline__ Pre<C> rheology(const Moments<C>& mo, const Coll<C>& 
         for (int a = 0; a < 3; ++a) r.u[a] = mo.j[a] * irho + C(0.5) * p.g[a];
         C t[6];
         noneq_second<LAT>(mo, r.rho, r.u, t);
+        // known flow axis: drop its normal component before the deviator
+        if (p.axis == 1) t[0] = C(0);
+        if (p.axis == 2) t[1] = C(0);
+        if (p.axis == 3) t[2] = C(0);
         const C tr = (D == 3) ? t[0] + t[1] + t[2] : t[0] + t[1];
         const C trd = tr / C(D);
         t[0] -= trd;

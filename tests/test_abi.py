@@ -63,6 +63,8 @@ def _desc(**kw):
     ({}, dict(op="PR", gamma_c=0.0)),
     ({}, dict(op="PR", lambda_trt=0.0)),
     ({}, dict(fp16_scale_log2=30)),
+    ({}, dict(flow_axis=4)),
+    ({}, dict(flow_axis=-1)),
     ({}, dict(fallback_band=-1.0)),
 ])
 def test_create_rejects_invalid(kw, rkw):

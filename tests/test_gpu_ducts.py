@@ -1,0 +1,149 @@
+"""Duct validation suite on the GPU (D3Q27, Sec. 4.2-4.4): the H = 63
+Bingham square duct against the spectral reference of Sec. 4.4, the
+convergence orders of Sec. 4.4 (square duct second order, circular duct
+first order through its staircase wall), the flow-axis correction of Sec.
+4.2.2 (IR transverse currents, PR plug viscosity), the early transient of
+Sec. 4.4 (reversed flow in PR, not in IR), and FP64 parity with the oracle
+with the correction switched on.
+
+Configuration of Sec. 4.4 (reading: the printed g and sigma_y of the
+transient paragraph are swapped; g = 2.7e-7, sigma_y = 1.7e-6 is the set
+that gives Hg = 432, Bi = 0.4 and the printed maximal velocity 2.5e-3):
+nu_p = 0.0125, axis along z, one periodic layer, bounce-back side walls.
+Steady state: max |u| changing by at most 1e-11 (relative) over 20000 steps.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from support import l2rel, run_pair
+
+pytestmark = pytest.mark.gpu
+
+NU = 0.0125
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")))
+
+
+def _duct(D, op, g, sy, m=0.0, axis=0, mask=None):
+    from paper_1610_01388_amd import lbm
+    dom = lbm.Domain("D3Q27", (D, D, 1), (0, 0, 1), op, NU, sy, m=m, g=(0.0, 0.0, g), flow_axis=axis)
+    if mask is not None:
+        dom.set_mask(mask)
+    return dom
+
+
+def _steady(dom, chunk=20000, tol=1e-11, cap=3_000_000):
+    prev, n = None, 0
+    while n < cap:
+        dom.step(chunk)
+        n += chunk
+        u = dom.monitors()["umax"]
+        if prev is not None and abs(u - prev) <= tol * u:
+            return u
+        prev = u
+    raise AssertionError(f"no steady state within {cap} steps")
+
+
+def _circle(D):
+    yy, xx = np.mgrid[0:D, 0:D]
+    R = D / 2.0
+    return (((xx + 0.5 - R) ** 2 + (yy + 0.5 - R) ** 2) > R * R).astype(np.uint8).reshape(-1)
+
+
+def _g(D):
+    """Body force at fixed Hagen number Hg = g D^3 / nu^2 = 432 (Sec. 4.4)."""
+    return 432.0 * NU * NU / D ** 3
+
+
+@pytest.mark.parametrize("op,m", [("IR", 0.0), ("PR", 1e8)])
+def test_square_duct_against_spectral_reference(op, m):
+    ref = GOLD["spectral_square_duct_re"]["value"]
+    u = _steady(_duct(63, op, 2.7e-7, 1.7e-6, m=m))
+    Re = u * 63 / NU
+    print(f"{op}: Re {Re:.6f} vs spectral {ref} ({(Re - ref) / ref:+.2e})", flush=True)
+    assert abs(Re - ref) <= 2e-3 * ref
+
+
+def test_convergence_orders():
+    """Errors at D = 15, 31, 63 with Hg = 432 (and Bi = 0.4 for Bingham):
+    square duct against the Newtonian closed form with c_max (Eq. 44 at
+    Bi = 0), circular duct against Eq. 43."""
+    cmax = GOLD["square_duct_c_max"]["value"]
+    errs = {"square": [], "circle": [], "circle_bingham": []}
+    for D in (15, 31, 63):
+        g, R = _g(D), D / 2.0
+        u = _steady(_duct(D, "IR", g, 0.0))
+        errs["square"].append(abs(u / (cmax * g * D * D / (16 * NU)) - 1))
+        u = _steady(_duct(D, "IR", g, 0.0, mask=_circle(D)))
+        errs["circle"].append(abs(u / (g * R * R / (4 * NU)) - 1))
+        sy = 0.4 * g * D / 4
+        u = _steady(_duct(D, "IR", g, sy, mask=_circle(D)))
+        errs["circle_bingham"].append(abs(u / (g * R * R / (4 * NU) * (1 - 2 * sy / g / R) ** 2) - 1))
+    order = {k: np.log(v[0] / v[-1]) / np.log(63 / 15) for k, v in errs.items()}
+    print("errors", errs, "orders", order, flush=True)
+    assert order["square"] >= 1.8                  # second order (Sec. 4.4)
+    assert 0.7 <= order["circle"] <= 1.6            # first order: staircase wall
+    assert 0.7 <= order["circle_bingham"] <= 1.6
+    assert errs["circle"][-1] < 0.02 and errs["circle_bingham"][-1] < 0.03
+
+
+def test_flow_axis_correction_ir_currents():
+    """Sec. 4.2.2: T_zz redistributed by the deviator drives transverse
+    currents; with it dropped they vanish to rounding, and U_max moves by
+    less than 1e-6 (relative)."""
+    out = {}
+    for axis in (0, 3):
+        dom = _duct(63, "IR", 2.7e-7, 1.7e-6, axis=axis)
+        u = _steady(dom)
+        _, uu, _, _ = dom.moments()
+        out[axis] = (u, float(np.abs(uu[:2]).max()))
+    print(out, flush=True)
+    assert out[0][1] > 1e-7 * out[0][0]
+    assert out[3][1] < 1e-13 * out[3][0]
+    assert abs(out[3][0] - out[0][0]) < 1e-6 * out[0][0]
+
+
+@pytest.mark.parametrize("m", [1e6, 1e9])
+def test_flow_axis_correction_pr_viscosity(m):
+    """Sec. 4.2.2: without the correction the plug viscosity stays below its
+    limit nu_p + m sigma_y / rho, more so as m grows; with it the limit is
+    reached exactly."""
+    sy = 1.7e-6
+    lim = NU + m * sy
+    got = {}
+    for axis in (0, 3):
+        dom = _duct(63, "PR", 2.7e-7, sy, m=m, axis=axis)
+        _steady(dom)
+        _, _, nu_app, _ = dom.moments()
+        got[axis] = float(nu_app.max())
+    print(m, got, lim, flush=True)
+    assert abs(got[3] - lim) <= 1e-9 * lim
+    assert got[0] < (1 - 1e-3) * lim
+
+
+def test_transient_reversed_flow_in_pr_only():
+    """Sec. 4.4: after an impulsive start, PR shows spurious fluctuations that
+    reverse the flow locally; IR does not.  The smallest axial velocity over
+    the first 200 steps (sampled every 5)."""
+    mins = {}
+    for op, m in (("IR", 0.0), ("PR", 1e8)):
+        dom = _duct(63, op, 2.7e-7, 1.7e-6, m=m)
+        lo = np.inf
+        for _ in range(40):
+            dom.step(5)
+            _, uu, _, _ = dom.moments()
+            lo = min(lo, float(uu[2].min()))
+        mins[op] = lo
+    print(mins, flush=True)
+    assert mins["PR"] < 0.0 <= mins["IR"]
+
+
+@pytest.mark.parametrize("op", ["IR", "PR"])
+def test_parity_with_flow_axis_correction(op):
+    dims, per = (23, 17, 5), (0, 0, 1)
+    ref, got, _, _ = run_pair(2, dims, per, op, 40, nu_p=0.05, sigma_y=2e-4, m=1e5, g=(0.0, 0.0, 3e-5),
+                              seed=77, flow_axis=3)
+    assert l2rel(got[1], ref[1]) <= 1e-10
+    assert np.array_equal(got[3], ref[3])
