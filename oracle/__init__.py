@@ -22,7 +22,7 @@ LIB = os.path.join(HERE, "liboracle.so")
 _LIB_OVERRIDE = os.environ.get("LBM_ORACLE_LIB")
 
 D2Q9, D3Q19, D3Q27 = 0, 1, 2
-PR, IR, BGK = 0, 1, 2
+PR, IR, BGK, PRI = 0, 1, 2, 3
 
 
 def build(force: bool = True) -> str:
@@ -79,6 +79,7 @@ def lib():
                                      ctypes.c_double, dp, dp]
         L.orc_collide_ir.argtypes = [ctypes.c_int, ctypes.POINTER(Rheology), dp, dp, dp]
         L.orc_collide_bgk.argtypes = [ctypes.c_int, ctypes.POINTER(Rheology), dp, dp, dp]
+        L.orc_collide_pri.argtypes = [ctypes.c_int, ctypes.POINTER(Rheology), dp, dp, dp]
         L.orc_nu_app.argtypes = [ctypes.POINTER(Rheology), ctypes.c_double, ctypes.c_double]
         L.orc_nu_app.restype = ctypes.c_double
         L.orc_create.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ip,
@@ -142,6 +143,17 @@ def collide_ir(lattice, rh, fbar):
     return fpost[:q].copy(), {"u": out[0:3].copy(), "T": out[3], "unyielded": bool(out[4]),
                               "s": out[5:14].reshape(3, 3).copy(),
                               "sigma": out[14:23].reshape(3, 3).copy()}
+
+
+def collide_pri(lattice, rh, fbar):
+    """PR with the implicit relaxation-time update (no tau state)."""
+    fbar = np.ascontiguousarray(fbar, dtype=np.float64)
+    fpost = np.zeros(27)
+    out = np.zeros(32)
+    lib().orc_collide_pri(lattice, ctypes.byref(rh), _dp(fbar), _dp(fpost), _dp(out))
+    q = fbar.size
+    return fpost[:q].copy(), {"tau": out[0], "nu_app": out[1], "gamma": out[2],
+                              "u": out[3:6].copy(), "unyielded": bool(out[6])}
 
 
 def collide_bgk(lattice, rh, fbar):

@@ -344,6 +344,62 @@ static void collide_bgk(const lattice_t* L, const orc_rheology* rh, const double
         for (int a = 0; a < 3; ++a) out[a] = u[a] + 0.5 * rh->g[a];
 }
 
+/* ---------------------------------------------------------------------------
+ * PR with the implicit relaxation-time update (Sec. 3): instead of taking
+ * the strain rate with the previous step's relaxation time, the collision
+ * uses the relaxation time tau that reproduces itself: the strain rate of
+ * Eq. 24 evaluated with tau gives, through Eqs. 36-37 and Eq. 15,
+ * tau = 1/2 + nu_app / cs^2 again.  With G the strain rate Eq. 24 gives for
+ * tau = 1, the strain rate at tau is G / tau, so tau is a root of
+ *   F(tau) = tau - 1/2 - nu_app(G / tau) / cs^2,
+ * which lies in [1/2 + nu_p / cs^2, 1/2 + nu_0 / cs^2] (nu_p <= nu_app <= nu_0)
+ * where F changes sign.  It is found by bisection to the last bit, and the
+ * collision is then the PR collision with that tau in place of the
+ * previous one.
+ * ------------------------------------------------------------------------- */
+static double strain_rate_unit_tau(const lattice_t* L, const orc_rheology* rh, const double* fbar)
+{
+    double rho, j[3], u[3], feq[QMAX], Pneq[3][3], D[3][3];
+    density_momentum(L, fbar, &rho, j);
+    for (int a = 0; a < 3; ++a) u[a] = j[a] / rho;
+    equilibrium(L, rho, u, feq);
+    second_moment_of_difference(L, fbar, feq, Pneq);
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) D[a][b] = -Pneq[a][b] / (2.0 * rho * CS2);
+    if (rh->flow_axis >= 1 && rh->flow_axis <= 3) D[rh->flow_axis - 1][rh->flow_axis - 1] = 0.0;
+    double DD = 0.0;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) DD += D[a][b] * D[a][b];
+    return sqrt(2.0 * DD);
+}
+
+static void collide_pri(const lattice_t* L, const orc_rheology* rh, const double* fbar,
+                        double* fpost, double* out)
+{
+    double rho = 0.0;
+    for (int i = 0; i < L->q; ++i) rho += fbar[i];
+    const double G = strain_rate_unit_tau(L, rh, fbar);
+    double lo = 0.5 + rh->nu_p / CS2;
+    double hi = 0.5 + (rh->nu_p + rh->m * rh->sigma_y / rho) / CS2;
+    for (int it = 0; it < 4000; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;  /* bracket is down to adjacent doubles */
+        const double F = mid - 0.5 - orc_nu_app(rh, G / mid, rho) / CS2;
+        if (F > 0.0) hi = mid;
+        else lo = mid;
+    }
+    collide_pr(L, rh, fbar, 0.5 * (lo + hi), fpost, out);
+}
+
+int orc_collide_pri(int lattice, const orc_rheology* rh, const double* fbar,
+                    double* fpost, double* out)
+{
+    lattice_t L;
+    if (build_lattice(lattice, &L) < 0) return -1;
+    collide_pri(&L, rh, fbar, fpost, out);
+    return 0;
+}
+
 int orc_collide_pr(int lattice, const orc_rheology* rh, const double* fbar,
                    double tau_prev, double* fpost, double* out)
 {
@@ -489,8 +545,9 @@ static void collide_node(const orc_domain* dom, const double* fbar, double tau_p
                          double* nu_app, int* unyielded)
 {
     double out[23];
-    if (dom->rh.op == ORC_PR) {
-        collide_pr(&dom->L, &dom->rh, fbar, tau_prev, fpost, out);
+    if (dom->rh.op == ORC_PR || dom->rh.op == ORC_PRI) {
+        if (dom->rh.op == ORC_PR) collide_pr(&dom->L, &dom->rh, fbar, tau_prev, fpost, out);
+        else collide_pri(&dom->L, &dom->rh, fbar, fpost, out);
         *tau_new = out[0];
         *nu_app = out[1];
         for (int a = 0; a < 3; ++a) u_out[a] = out[3 + a];

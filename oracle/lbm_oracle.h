@@ -27,11 +27,13 @@ extern "C" {
 #endif
 
 enum { ORC_D2Q9 = 0, ORC_D3Q19 = 1, ORC_D3Q27 = 2 };
-enum { ORC_PR = 0, ORC_IR = 1, ORC_BGK = 2 };
+enum { ORC_PR = 0, ORC_IR = 1, ORC_BGK = 2, ORC_PRI = 3 };
 
-/* Rheology and forcing.  op: ORC_PR (Papanastasiou-regularised, TRT + EDM),
- * ORC_IR (implicitly-regularised), ORC_BGK (Newtonian BGK + EDM reference,
- * tau = 1/2 + 3 nu_p). */
+/* Rheology and forcing.  op: ORC_PR (Papanastasiou-regularised, TRT + EDM,
+ * explicit relaxation-time update), ORC_IR (implicitly-regularised),
+ * ORC_BGK (Newtonian BGK + EDM reference, tau = 1/2 + 3 nu_p), ORC_PRI (PR
+ * with the implicit relaxation-time update of Sec. 3: no state carried
+ * between steps). */
 typedef struct {
     int32_t op;
     int32_t flow_axis; /* 0: off; 1, 2, 3: the flow is known to be along x, y,
@@ -67,6 +69,9 @@ int orc_collide_pr(int lattice, const orc_rheology* rh, const double* fbar,
 int orc_collide_ir(int lattice, const orc_rheology* rh, const double* fbar,
                    double* fpost, double* out);
 int orc_collide_bgk(int lattice, const orc_rheology* rh, const double* fbar,
+                    double* fpost, double* out);
+/* PRI: out as PR (out[0] = the self-consistent relaxation time). */
+int orc_collide_pri(int lattice, const orc_rheology* rh, const double* fbar,
                     double* fpost, double* out);
 
 /* The PR apparent viscosity (Sec. 3.1, Eqs. 36-37). */

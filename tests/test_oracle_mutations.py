@@ -41,12 +41,16 @@ MUTATIONS = {
     "residual_unsquared": ("        num += d2;", "        num += sqrt(d2);"),
     "flow_axis_off_by_one": ("if (rh->flow_axis >= 1 && rh->flow_axis <= 3) T[rh->flow_axis - 1][rh->flow_axis - 1] = 0.0;",
                              "if (rh->flow_axis >= 1 && rh->flow_axis <= 3) T[rh->flow_axis % 3][rh->flow_axis % 3] = 0.0;"),
+    "pri_bisection_flipped": ("        if (F > 0.0) hi = mid;\n        else lo = mid;", "        if (F > 0.0) lo = mid;\n        else hi = mid;"),
+    "pri_bracket_without_density": ("double hi = 0.5 + (rh->nu_p + rh->m * rh->sigma_y / rho) / CS2;",
+                                    "double hi = 0.5 + (rh->nu_p + rh->m * rh->sigma_y) / CS2 * 0.5;"),
     "flow_axis_pr_ignored": ("if (rh->flow_axis >= 1 && rh->flow_axis <= 3) D[rh->flow_axis - 1][rh->flow_axis - 1] = 0.0;",
                              "if (0) D[rh->flow_axis - 1][rh->flow_axis - 1] = 0.0;"),
 }
 
 PIN_TESTS = ["tests/test_oracle_lattice.py", "tests/test_oracle_operators.py",
-             "tests/test_oracle_flows.py", "tests/test_oracle_residual.py", "tests/test_oracle_burnett.py"]
+             "tests/test_oracle_flows.py", "tests/test_oracle_residual.py", "tests/test_oracle_burnett.py",
+             "tests/test_oracle_pri.py"]
 
 
 @pytest.mark.parametrize("name", sorted(MUTATIONS))
