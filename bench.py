@@ -48,7 +48,7 @@ def algorithmic_bytes_per_node(lattice, op, precision):
     """Bytes one fluid-node update must move: read and write every population
     once, plus read and write the PR relaxation time."""
     b = 2 * Q[lattice] * PREC_BYTES[precision]
-    if op == "PR":
+    if op == "PR":  # PRI and IR keep no relaxation-time field
         b += 2 * (8 if precision == "FP64" else 4)
     return b
 
@@ -355,7 +355,10 @@ def main():
         f64_pr, ref_pr = run_form(torch, lbm, "PR FP64", case_pr, "FP64", mask, fluid, W, K)
         dense_ir, _ = run_form(torch, lbm, "IR FP64 dense layout", case, "FP64", mask, fluid, W, K, ref=ref_ir,
                                layout="DENSE")
-        forms += [f64_ir, f64_pr, dense_ir]
+        case_pri = dict(case_pr, op="PRI")
+        pri, _ = run_form(torch, lbm, "PRI FP64 (implicit tau update, no tau field)", case_pri, "FP64", mask, fluid,
+                          W, K)
+        forms += [f64_ir, f64_pr, dense_ir, pri]
         log("forms: FP32 storage and collision")
         forms.append(run_form(torch, lbm, "IR FP32", case, "FP32", mask, fluid, W, K, ref=ref_ir)[0])
         forms.append(run_form(torch, lbm, "PR FP32", case_pr, "FP32", mask, fluid, W, K, ref=ref_pr)[0])

@@ -56,7 +56,14 @@ typedef enum {
 } lbm_status;
 
 typedef enum { LBM_D2Q9 = 0, LBM_D3Q19 = 1, LBM_D3Q27 = 2 } lbm_lattice;
-typedef enum { LBM_PR = 0, LBM_IR = 1 } lbm_operator;
+/* LBM_PR: Papanastasiou-regularised TRT + EDM with the explicit relaxation-
+ * time update (Sec. 3, 3.1: the strain rate uses the previous step's tau,
+ * kept per node in the tau buffer).  LBM_IR: implicitly regularised (Sec.
+ * 2.3, 3.2).  LBM_PRI: the PR model with the implicit update of Sec. 3: the
+ * tau consistent with its own strain rate, found per node each step by
+ * bracketed Newton iterations; nothing is kept between steps (no tau
+ * buffer). */
+typedef enum { LBM_PR = 0, LBM_IR = 1, LBM_PRI = 2 } lbm_operator;
 /* Storage of the populations.  All three store deviations h_i = f_i - w_i
  * rho0.  FP64: h in double, collision in double.  FP32: h in float,
  * collision in float.  FP16: h_i * 2^k / w_i in IEEE half (k =
@@ -232,7 +239,8 @@ int lbm_destroy(lbm_domain* dom);
  * Every simulation is all-fluid inside its box (walls only through
  * non-periodic axes) and has its own sizes, operator and rheology; all
  * share one lattice, one precision, the AA scheme, the FP64-fallback flag
- * and the FP16 scale; each holds fewer than 2^31 / Q nodes.  One step is one persistent kernel launch over a work
+ * and the FP16 scale; each holds fewer than 2^31 / Q nodes and uses LBM_PR
+ * or LBM_IR.  One step is one persistent kernel launch over a work
  * list of 256-node tiles of all simulations; lbm_batch_step replays a
  * captured hipGraph of graph_steps such launches when it can.  The update
  * of each node is the same as lbm_step's (a simulation gives bitwise the

@@ -115,7 +115,7 @@ __global__ __launch_bounds__(256) void k_readout(const NodeArgs a)
     if (active) {
         C h[L::Q];
         gather<LAT, PREC>(a, k, x, y, z, h);
-        const C tau_prev = (OP == OP_PR) ? (C)((const T*)a.tau)[k] : C(0);
+        const C tau_prev = has_tau(OP) ? (C)((const T*)a.tau)[k] : C(0);
         mo = moments<LAT>(h);
         pr = rheology<LAT, OP>(mo, cp, tau_prev);
         out_velocity(mo, pr, cp, uo);
@@ -180,7 +180,7 @@ __global__ __launch_bounds__(256) void k_init(const NodeArgs a, double rho)
         const int slot = (a.layout == LAY_POST_SWAPPED) ? opp(i) : i;
         A[(int64_t)slot * a.S + k] = encode<PREC>((typename Store<PREC>::C)hdev, L::w[i], a.h16_inv);
     }
-    if (OP == OP_PR && a.tau) {
+    if (has_tau(OP) && a.tau) {
         const double nu0 = a.cd.nu_p + a.cd.m * a.cd.sigma_y / rho;
         ((T*)a.tau)[k] = (T)(0.5 + 3.0 * nu0);
     }
@@ -387,6 +387,9 @@ hipError_t launch_readout(int lat, int op, int prec, const NodeArgs& a, hipStrea
         if (op == OP_PR)
             hipLaunchKernelGGL((k_readout<decltype(L)::value, OP_PR, decltype(P)::value>), dim3(nblk(a.count)),
                                dim3(256), 0, s, a);
+        else if (op == OP_PRI)
+            hipLaunchKernelGGL((k_readout<decltype(L)::value, OP_PRI, decltype(P)::value>), dim3(nblk(a.count)),
+                               dim3(256), 0, s, a);
         else
             hipLaunchKernelGGL((k_readout<decltype(L)::value, OP_IR, decltype(P)::value>), dim3(nblk(a.count)),
                                dim3(256), 0, s, a);
@@ -399,6 +402,9 @@ hipError_t launch_init(int lat, int op, int prec, const NodeArgs& a, double rho,
     return dispatch_lat_prec(lat, prec, [&](auto L, auto P) {
         if (op == OP_PR)
             hipLaunchKernelGGL((k_init<decltype(L)::value, OP_PR, decltype(P)::value>), dim3(nblk(a.N)), dim3(256),
+                               0, s, a, rho);
+        else if (op == OP_PRI)
+            hipLaunchKernelGGL((k_init<decltype(L)::value, OP_PRI, decltype(P)::value>), dim3(nblk(a.N)), dim3(256),
                                0, s, a, rho);
         else
             hipLaunchKernelGGL((k_init<decltype(L)::value, OP_IR, decltype(P)::value>), dim3(nblk(a.N)), dim3(256),

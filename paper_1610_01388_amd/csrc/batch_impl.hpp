@@ -85,7 +85,7 @@ __device__ __forceinline__ void batch_tile(const BatchArgs& a, const BatchSim& s
         }
         T* tau = (T*)a.tau + sm.off_tau;
         C tau_prev = C(0);
-        if constexpr (OP == OP_PR) tau_prev = (C)tau[n];
+        if constexpr (has_tau(OP)) tau_prev = (C)tau[n];
 
         collide_node<LAT, OP, PREC>(h, tau_prev, a.fallback, sm.cd, cp, mo, pr, used_fb);
 
@@ -103,7 +103,7 @@ __device__ __forceinline__ void batch_tile(const BatchArgs& a, const BatchSim& s
             }
             B[idx] = encode<PREC>(h[i], L::w[i], a.h16_inv);
         }
-        if constexpr (OP == OP_PR) tau[n] = (T)pr.tau_p;
+        if constexpr (has_tau(OP)) tau[n] = (T)pr.tau_p;
     }
     if constexpr (MON)
         monitor_block<C>(active, mo, pr, cp, used_fb, a.partials + (int64_t)item * MP_COUNT,
@@ -129,6 +129,8 @@ __global__ __launch_bounds__(256) void k_batch_step(const BatchArgs a)
     for (int item = first; item < hi; item += stride) {
         const int sim = __builtin_amdgcn_readfirstlane(a.work[item]);
         const BatchSim& sm = a.sims[sim];
+        // PR or IR (the host rejects PRI for batches: its Newton solve would
+        // raise the register count of this shared kernel for every item)
         if (sm.op == OP_PR) batch_tile<LAT, OP_PR, PREC, PAT, MON>(a, sm, item);
         else batch_tile<LAT, OP_IR, PREC, PAT, MON>(a, sm, item);
         // the block reduction's LDS slots are read by thread 0 after its

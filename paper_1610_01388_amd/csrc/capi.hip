@@ -59,7 +59,7 @@ static_assert((int)LAYOUT_COMPACT == (int)LBM_COMPACT && (int)LAYOUT_DENSE == (i
               "kernel layout codes must equal the C ABI's lbm_layout values");
 static_assert((int)PREC_F64 == (int)LBM_FP64 && (int)PREC_F32 == (int)LBM_FP32 && (int)PREC_F16 == (int)LBM_FP16,
               "kernel precision codes must equal the C ABI's lbm_precision values");
-static_assert((int)OP_PR == (int)LBM_PR && (int)OP_IR == (int)LBM_IR,
+static_assert((int)OP_PR == (int)LBM_PR && (int)OP_IR == (int)LBM_IR && (int)OP_PRI == (int)LBM_PRI,
               "kernel operator codes must equal the C ABI's lbm_operator values");
 
 int lattice_q(int lat) { return lat == 0 ? 9 : lat == 1 ? 19 : lat == 2 ? 27 : -1; }
@@ -89,13 +89,13 @@ int check_desc(const lbm_desc* d)
 int check_rheology(const lbm_rheology* r)
 {
     if (!r) return fail(LBM_EINVAL, "rheology is NULL");
-    if (r->op != LBM_PR && r->op != LBM_IR) return fail(LBM_EINVAL, "unknown operator %d", r->op);
+    if (r->op != LBM_PR && r->op != LBM_IR && r->op != LBM_PRI) return fail(LBM_EINVAL, "unknown operator %d", r->op);
     if (!(r->nu_p > 0)) return fail(LBM_EINVAL, "nu_p must be > 0 (tau > 1/2)");
     if (!(r->sigma_y >= 0)) return fail(LBM_EINVAL, "sigma_y must be >= 0");
     if (!(r->rho0 > 0)) return fail(LBM_EINVAL, "rho0 must be > 0");
     for (int a = 0; a < 3; ++a)
         if (!std::isfinite(r->g[a])) return fail(LBM_EINVAL, "body force must be finite");
-    if (r->op == LBM_PR) {
+    if (r->op == LBM_PR || r->op == LBM_PRI) {
         if (!(r->m >= 0)) return fail(LBM_EINVAL, "m must be >= 0");
         if (!(r->gamma_c > 0)) return fail(LBM_EINVAL, "gamma_c must be > 0");
         if (!(r->lambda_trt > 0)) return fail(LBM_EINVAL, "lambda_trt must be > 0");
@@ -1157,6 +1157,8 @@ int batch_validate(const lbm_desc* descs, const lbm_rheology* rh, int32_t count)
         if (descs[k].lattice != descs[0].lattice || descs[k].precision != descs[0].precision)
             return fail(LBM_EINVAL, "all simulations of a batch share one lattice and one precision");
         if (descs[k].scheme != LBM_AA) return fail(LBM_EINVAL, "batches use the AA scheme");
+        if (rh[k].op != LBM_PR && rh[k].op != LBM_IR)
+            return fail(LBM_EINVAL, "simulation %d: batches take the PR and IR operators", k);
         if ((int64_t)descs[k].nx * descs[k].ny * descs[k].nz * lattice_q(descs[k].lattice) >= ((int64_t)1 << 31))
             return fail(LBM_EINVAL, "simulation %d: batched simulations need Q * nodes < 2^31", k);
         if (rh[k].fp64_fallback != rh[0].fp64_fallback || rh[k].fp16_scale_log2 != rh[0].fp16_scale_log2)

@@ -14,7 +14,15 @@
 
 namespace lbm {
 
-enum { OP_PR = 0, OP_IR = 1 };
+// PR: Papanastasiou-regularised with the explicit relaxation-time update
+// (the strain rate uses the previous step's tau, kept per node); IR:
+// implicitly regularised; PRI: PR with the implicit update of Sec. 3 (the
+// tau consistent with its own strain rate, found per node; no state).
+enum { OP_PR = 0, OP_IR = 1, OP_PRI = 2 };
+// TRT + EDM with a Papanastasiou viscosity
+__host__ __device__ constexpr bool pr_family(int op) { return op != OP_IR; }
+// carries a relaxation-time field from step to step
+__host__ __device__ constexpr bool has_tau(int op) { return op == OP_PR; }
 
 __device__ __forceinline__ double d_sqrt(double v) { return sqrt(v); }
 __device__ __forceinline__ float d_sqrt(float v) { return sqrtf(v); }
@@ -101,12 +109,53 @@ __device__ __forceinline__ C frob2(const C (&t)[6])
     return t[0] * t[0] + t[1] * t[1] + t[2] * t[2] + C(2) * (t[3] * t[3] + t[4] * t[4] + t[5] * t[5]);
 }
 
+// PRI: the relaxation time tau with tau = 1/2 + 3 nu_app(G / tau), G being
+// the strain rate Eq. 24 gives at tau = 1.  F(tau) = tau - 1/2 - 3 nu_app(G /
+// tau) is convex in tau and changes sign once on [1/2 + 3 nu_p, 1/2 + 3
+// nu_0]; Newton's method from the upper end, kept inside the shrinking
+// bracket (bisection whenever a step would leave it), stops when a step is
+// below the precision's resolution.
+template <class C>
+__device__ __forceinline__ C implicit_tau(C G, const Coll<C>& p, C irho)
+{
+    const C s = p.sigma_y * irho;
+    const C nu0 = p.nu_p + p.m * s;
+    const C nuc = p.nu_p + s * p.pr_ec;
+    C lo = C(0.5) + C(3) * p.nu_p;
+    C hi = C(0.5) + C(3) * nu0;
+    C x = hi;
+    const C tol = sizeof(C) == 8 ? C(1e-14) : C(2e-7);
+    for (int it = 0; it < 64; ++it) {
+        const C gam = G / x;
+        C nu, dnu;  // nu_app(gam) and d nu_app / d gam
+        if (gam >= p.gamma_c) {
+            const C em = -d_expm1(-p.m * gam);  // 1 - exp(-m gam)
+            nu = p.nu_p + s * em / gam;
+            dnu = s / gam * (p.m * (C(1) - em) - em / gam);
+        } else {
+            nu = nu0 + (gam / p.gamma_c) * (nuc - nu0);
+            dnu = (nuc - nu0) / p.gamma_c;
+        }
+        const C F = x - C(0.5) - C(3) * nu;
+        if (F > C(0)) hi = x;
+        else lo = x;
+        const C dF = C(1) + C(3) * dnu * G / (x * x);
+        C xn = x - F / dF;
+        if (!(xn > lo && xn < hi)) xn = C(0.5) * (lo + hi);
+        const bool done = fabs(xn - x) <= tol * x || hi - lo <= tol * hi;
+        x = xn;
+        if (done) break;
+    }
+    return x;
+}
+
 // Rheology: everything up to, but not including, the relaxation.
 //  PR (Sec. 2.2 Eq. 24, Sec. 3.1 Eqs. 36-37, Sec. 2.1): D from the
 //   non-equilibrium second moment at the bare velocity with the previous
 //   step's tau (density kept, as in Eq. 33), gamma = sqrt(2 D:D) on the full
 //   tensor, nu_app with the linear interpolation below gamma_c (denominator
 //   gamma_c), tau_even = 1/2 + 3 nu_app, tau_odd from Lambda.
+//  PRI: as PR with tau_prev replaced by implicit_tau.
 //  IR (Sec. 2.3, 3.2): T = sum c c (f - f_eq + Phi/2) at u = (j + F/2)/rho,
 //   deviatoric part (trace / d), yielded iff |dev T| > sqrt(2) sigma_y,
 //   A = -sigma + s/2 = lambda dev T with the closed forms of Eqs. 39-40.
@@ -117,12 +166,23 @@ __device__ __forceinline__ Pre<C> rheology(const Moments<C>& mo, const Coll<C>& 
     Pre<C> r;
     r.rho = p.rho0 + mo.drho;
     const C irho = C(1) / r.rho;
-    if (OP == OP_PR) {
+    if (pr_family(OP)) {
 #pragma unroll
         for (int a = 0; a < 3; ++a) r.u[a] = mo.j[a] * irho;
         C t[6];
         noneq_second<LAT>(mo, r.rho, r.u, t);
-        const C coef = C(-1.5) / (r.rho * tau_prev);  // -1 / (2 rho cs^2 tau)
+        C tau_s = tau_prev;
+        if (OP == OP_PRI) {  // strain rate at tau = 1, then the self-consistent tau
+            const C c1 = C(-1.5) * irho;
+            C d1[6];
+#pragma unroll
+            for (int a = 0; a < 6; ++a) d1[a] = c1 * t[a];
+            if (p.axis == 1) d1[0] = C(0);
+            if (p.axis == 2) d1[1] = C(0);
+            if (p.axis == 3) d1[2] = C(0);
+            tau_s = implicit_tau(d_sqrt(C(2) * frob2(d1)), p, irho);
+        }
+        const C coef = C(-1.5) / (r.rho * tau_s);  // -1 / (2 rho cs^2 tau)
         C dd[6];
 #pragma unroll
         for (int a = 0; a < 6; ++a) dd[a] = coef * t[a];
@@ -189,7 +249,7 @@ __device__ __forceinline__ void relax(C (&h)[Lattice<LAT>::Q], const Moments<C>&
     using L = Lattice<LAT>;
     const C* u = r.u;
     const C uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-    if (OP == OP_PR) {
+    if (pr_family(OP)) {
         const C om_p = C(1) / r.tau_p;
         const C om_m = C(1) / r.tau_m;
         const C ug = p.g[0] * (C(2) * u[0] + p.g[0]) + p.g[1] * (C(2) * u[1] + p.g[1]) +

@@ -196,7 +196,7 @@ __global__ __launch_bounds__(256) void k_step(const StepArgs a)
             }
             h[i] = decode<PREC>(A[idx], L::w[i], a.h16_scale);
         }
-        if constexpr (OP == OP_PR) tau_prev = (C)((const T*)a.tau)[n];
+        if constexpr (has_tau(OP)) tau_prev = (C)((const T*)a.tau)[n];
 
         collide_node<LAT, OP, PREC>(h, tau_prev, a.fallback, a.cd, cp, mo, pr, used_fb);
 
@@ -219,7 +219,7 @@ __global__ __launch_bounds__(256) void k_step(const StepArgs a)
             }
             B[idx] = encode<PREC>(h[i], L::w[i], a.h16_inv);
         }
-        if constexpr (OP == OP_PR) ((T*)a.tau)[n] = (T)pr.tau_p;
+        if constexpr (has_tau(OP)) ((T*)a.tau)[n] = (T)pr.tau_p;
     }
 
     if constexpr (MON)
@@ -358,7 +358,7 @@ __global__ __launch_bounds__(256) void k_step_compact(const StepArgs a, const ui
             }
             h[i] = decode<PREC>(A[idx], L::w[i], a.h16_scale);
         }
-        if constexpr (OP == OP_PR) tau_prev = (C)((const T*)a.tau)[k];
+        if constexpr (has_tau(OP)) tau_prev = (C)((const T*)a.tau)[k];
 
         collide_node<LAT, OP, PREC>(h, tau_prev, a.fallback, a.cd, cp, mo, pr, used_fb);
 
@@ -386,7 +386,7 @@ __global__ __launch_bounds__(256) void k_step_compact(const StepArgs a, const ui
             }
             B[idx] = encode<PREC>(h[i], L::w[i], a.h16_inv);
         }
-        if constexpr (OP == OP_PR) ((T*)a.tau)[k] = (T)pr.tau_p;
+        if constexpr (has_tau(OP)) ((T*)a.tau)[k] = (T)pr.tau_p;
     }
     if constexpr (MON)
         monitor_block<C>(active, mo, pr, cp, used_fb, a.partials + (int64_t)tile * MP_COUNT, a.uprev, k, St);
@@ -424,7 +424,7 @@ __global__ __launch_bounds__(256) void k_local_slots(const StepArgs a)
             h[i] = decode<PREC>(NT ? ld_stream(p) : *p, L::w[i], a.h16_scale);
         }
         C tau_prev = C(0);
-        if constexpr (OP == OP_PR) tau_prev = (C)((const T*)a.tau)[k];
+        if constexpr (has_tau(OP)) tau_prev = (C)((const T*)a.tau)[k];
 
         collide_node<LAT, OP, PREC>(h, tau_prev, a.fallback, a.cd, cp, mo, pr, used_fb);
 
@@ -436,7 +436,7 @@ __global__ __launch_bounds__(256) void k_local_slots(const StepArgs a)
             if constexpr (NT) st_stream(v, p);
             else *p = v;
         }
-        if constexpr (OP == OP_PR) ((T*)a.tau)[k] = (T)pr.tau_p;
+        if constexpr (has_tau(OP)) ((T*)a.tau)[k] = (T)pr.tau_p;
     }
     if constexpr (MON)
         monitor_block<C>(active, mo, pr, cp, used_fb, a.partials + (int64_t)blockIdx.x * MP_COUNT, a.uprev, k, St);
@@ -490,6 +490,12 @@ hipError_t launch_step_lattice(int op, int prec, int pat, bool mon, int layout, 
         case PREC_F64: return go_pat<LAT, OP_PR, PREC_F64>(pat, mon, layout, a, s);
         case PREC_F32: return go_pat<LAT, OP_PR, PREC_F32>(pat, mon, layout, a, s);
         case PREC_F16: return go_pat<LAT, OP_PR, PREC_F16>(pat, mon, layout, a, s);
+        }
+    } else if (op == OP_PRI) {
+        switch (prec) {
+        case PREC_F64: return go_pat<LAT, OP_PRI, PREC_F64>(pat, mon, layout, a, s);
+        case PREC_F32: return go_pat<LAT, OP_PRI, PREC_F32>(pat, mon, layout, a, s);
+        case PREC_F16: return go_pat<LAT, OP_PRI, PREC_F16>(pat, mon, layout, a, s);
         }
     } else {
         switch (prec) {

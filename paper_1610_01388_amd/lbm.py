@@ -18,7 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblbm.so")
 
 LATTICES = {"D2Q9": 0, "D3Q19": 1, "D3Q27": 2}
-OPERATORS = {"PR": 0, "IR": 1}
+OPERATORS = {"PR": 0, "IR": 1, "PRI": 2}
 PRECISIONS = {"FP64": 0, "FP32": 1, "FP16": 2}
 SCHEMES = {"AB": 0, "AA": 1}
 LAYOUTS = {"COMPACT": 0, "DENSE": 1}

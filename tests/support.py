@@ -7,7 +7,7 @@ import oracle
 from paper_1610_01388_amd import inputs
 
 LAT_NAMES = {0: "D2Q9", 1: "D3Q19", 2: "D3Q27"}
-OP_IDS = {"PR": oracle.PR, "IR": oracle.IR}
+OP_IDS = {"PR": oracle.PR, "IR": oracle.IR, "PRI": oracle.PRI}
 
 
 def perm_lib_from_oracle(lat):

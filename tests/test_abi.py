@@ -128,3 +128,16 @@ def test_struct_layouts_match_header(tmp_path):
         assert got[(name, "size")] == ctypes.sizeof(cls), name
         for f in cls._fields_:
             assert got[(name, f[0])] == getattr(cls, f[0]).offset, (name, f[0])
+
+
+def test_implicit_pr_needs_no_tau_and_batches_reject_it():
+    d = _desc(lattice="D3Q19", dims=(8, 9, 10))
+    s = lbm.lbm_query_sizes(d, lbm.make_rheology("PRI", 0.1, 1e-4, 1e4))
+    assert s.tau_bytes == 0
+    assert lbm.lbm_query_sizes(d, lbm.make_rheology("PR", 0.1, 1e-4, 1e4)).tau_bytes > 0
+    h = lbm.lbm_create(d, lbm.make_rheology("PRI", 0.1, 1e-4, 1e4))
+    lbm.lbm_destroy(h)
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_batch_query_sizes([lbm.make_desc("D3Q19", (8, 8, 4), (0, 0, 1), "FP32", "AA")],
+                                  [lbm.make_rheology("PRI", 0.1, 1e-4, 1e4)])
+    assert e.value.code == -1

@@ -1,0 +1,108 @@
+"""GPU tests of the PR model with the implicit relaxation-time update of
+Sec. 3 (operator PRI; the next-row N3): FP64 parity with the oracle (which
+finds the same root by bisection) on every lattice, both schemes and both
+layouts, with solids and ragged tiles; the reduced-precision bars; the
+Bingham channel steady state against explicit PR and the 1-D regularised
+solution; no relaxation-time field anywhere (checkpoints included)."""
+import numpy as np
+import pytest
+
+from paper_1610_01388_amd import inputs
+from support import LAT_NAMES, l2rel, perm_lib_from_oracle, random_mask, random_state, run_pair
+from test_oracle_flows import _channel_regularised
+
+pytestmark = pytest.mark.gpu
+
+CASES = [(0, (70, 37, 1), (1, 0, 1)), (1, (70, 13, 9), (1, 0, 1)), (2, (37, 11, 13), (0, 1, 1))]
+
+
+@pytest.mark.parametrize("layout", ["COMPACT", "DENSE"])
+@pytest.mark.parametrize("scheme", ["AA", "AB"])
+@pytest.mark.parametrize("lat,dims,per", CASES)
+def test_pri_parity_fp64(lat, dims, per, scheme, layout):
+    N = int(np.prod(dims))
+    mask = random_mask(N, 500 + lat, 0.15)
+    ref, got, _, _ = run_pair(lat, dims, per, "PRI", 31, mask=mask, seed=13, scheme=scheme, m=1e4,
+                              sigma_y=5e-4, gpu_kw={"layout": layout})
+    fluid = mask == 0
+    assert l2rel(got[1], ref[1]) <= 1e-10
+    assert np.max(np.abs(got[0] - ref[0])[fluid]) <= 1e-12
+    # the yield flag may differ only where the stress sits within rounding of sigma_y
+    assert np.sum(got[3] != ref[3]) <= 2
+    assert l2rel(got[2][fluid], ref[2][fluid]) <= 1e-9  # apparent viscosity
+
+
+@pytest.mark.parametrize("precision", ["FP32", "FP16"])
+def test_pri_reduced_precision(precision):
+    lat, dims, per = 2, (37, 11, 13), (1, 0, 1)
+    N = int(np.prod(dims))
+    mask = random_mask(N, 91, 0.15)
+    kw = {"layout": "COMPACT"}
+    if precision == "FP16":
+        kw.update(fp64_fallback=True, fallback_band=1.0, fp16_scale_log2=14)
+    ref, got, _, _ = run_pair(lat, dims, per, "PRI", 60, mask=mask, seed=17, precision=precision, gpu_kw=kw)
+    tol = {"FP32": 2e-5, "FP16": 5e-3}[precision]
+    assert l2rel(got[1], ref[1]) <= tol
+
+
+def test_pri_channel_steady_state():
+    """D2Q9 4 x 64 Bingham channel (Bi = 1, m = 1e4): PRI converges to the
+    1-D regularised solution of Eq. 36 and to explicit PR's steady state."""
+    from paper_1610_01388_amd import lbm
+    H, g, nu, m = 64, 1e-5, 0.1, 1e4
+    sy = g * H / 4.0
+    ux = {}
+    for op in ("PR", "PRI"):
+        dom = lbm.Domain("D2Q9", (4, H, 1), (1, 0, 1), op, nu, sy, m=m, g=(g, 0, 0))
+        dom.step(40000)
+        _, u, _, _ = dom.moments()
+        ux[op] = u[0].reshape(H, 4)
+    ref = _channel_regularised(H, g, nu, sy, m)
+    assert np.max(np.abs(ux["PRI"] - ref[:, None])) < 1.5e-3 * ref.max()
+    assert np.max(np.abs(ux["PRI"] - ux["PR"])) < 1e-6 * ref.max()
+
+
+def test_pri_has_no_tau_field_and_checkpoints():
+    from paper_1610_01388_amd import lbm
+    lat, dims, per = 2, (37, 11, 13), (1, 0, 1)
+    N = int(np.prod(dims))
+    mask = random_mask(N, 4, 0.2)
+    mk = lambda: lbm.Domain("D3Q27", dims, per, "PRI", 0.1, 5e-4, m=1e4, g=(2e-5, 0, 0))
+    a = mk()
+    assert a.tau is None
+    a.set_mask(mask)
+    a.step(25)
+    blob = a.save()
+    a.step(26)
+    b = mk()
+    b.load(blob)
+    b.step(26)
+    assert np.array_equal(a.read_populations()[0], b.read_populations()[0])
+
+
+def test_pri_full_size_porous_two_steps():
+    """The bench geometry (D3Q27 256^3 pack, FP64, AA, compact) with PRI from
+    a seeded random state: two steps against two oracle steps."""
+    import oracle
+    from paper_1610_01388_amd import lbm
+    n = 256
+    mask, _ = inputs.sphere_pack((n, n, n), 8.0, 0.7, seed=1)
+    case = inputs.porous_case("PR", n=n, Bi=1.0)
+    P0, tau0 = random_state(2, n ** 3, 23, amp=1e-3)
+    P0 *= (1 - mask)[None, :]
+    rh = oracle.rheology(oracle.PRI, case["nu_p"], case["sigma_y"], case["m"], 1e-8, 0.25, case["g"])
+    od = oracle.Domain(2, case["dims"], case["periodic"], rh, mask)
+    od.set_state(P0, tau0)
+    od.step(2)
+    rho_o, u_o, _, _ = od.moments()
+    od.close()
+    dom = lbm.Domain("D3Q27", case["dims"], case["periodic"], "PRI", case["nu_p"], case["sigma_y"], m=case["m"],
+                     g=case["g"])
+    dom.set_mask(mask)
+    dom.write_populations(P0[perm_lib_from_oracle(2)])
+    del P0
+    dom.step(2)
+    rho_g, u_g, _, _ = dom.moments()
+    dom.close()
+    assert l2rel(u_g, u_o) <= 1e-10
+    assert np.max(np.abs(rho_g - rho_o)[mask == 0]) <= 1e-12
