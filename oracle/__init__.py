@@ -39,15 +39,20 @@ class Rheology(ctypes.Structure):
     _fields_ = [("op", ctypes.c_int32), ("flow_axis", ctypes.c_int32),
                 ("nu_p", ctypes.c_double), ("sigma_y", ctypes.c_double),
                 ("m", ctypes.c_double), ("gamma_c", ctypes.c_double),
-                ("lambda_", ctypes.c_double), ("g", ctypes.c_double * 3)]
+                ("lambda_", ctypes.c_double), ("g", ctypes.c_double * 3),
+                ("mrt_bulk", ctypes.c_double), ("mrt_even", ctypes.c_double)]
 
 
-def rheology(op, nu_p, sigma_y=0.0, m=0.0, gamma_c=1e-8, lam=0.25, g=(0.0, 0.0, 0.0), flow_axis=0):
+def rheology(op, nu_p, sigma_y=0.0, m=0.0, gamma_c=1e-8, lam=0.25, g=(0.0, 0.0, 0.0), flow_axis=0,
+             mrt_bulk=0.0, mrt_even=0.0):
     """flow_axis: 0 off, 1/2/3 = x/y/z -- drop the axis-normal component
-    from the collision (Sec. 4.2.2)."""
+    from the collision (Sec. 4.2.2).  mrt_bulk, mrt_even: MRT rates of the
+    bulk moment and of the even moments of order >= 4 (0: TRT)."""
     r = Rheology()
     r.op = op
     r.flow_axis = flow_axis
+    r.mrt_bulk = mrt_bulk
+    r.mrt_even = mrt_even
     r.nu_p = nu_p
     r.sigma_y = sigma_y
     r.m = m

@@ -28,7 +28,15 @@ typedef struct {
     int c[QMAX][3];
     double w[QMAX];
     int opp[QMAX];
+    /* MRT moment basis (Sec. 2.1): row k of M is mrt[k][i], its weighted norm
+     * sum_i w_i mrt[k][i]^2 is mrt_n[k], its rate group is mrt_group[k]. */
+    double mrt[QMAX][QMAX];
+    double mrt_n[QMAX];
+    int mrt_group[QMAX];
 } lattice_t;
+
+enum { MRT_CONSERVED = 0, MRT_BULK = 1, MRT_SHEAR = 2, MRT_ODD = 3, MRT_EVEN = 4 };
+static void build_mrt_basis(lattice_t* L);
 
 /* The three velocity sets of Sec. 4.1.  The paper does not list them; these are
  * the standard sets: every c in {-1,0,1}^d, restricted to |c|^2 <= 2 for D3Q19,
@@ -71,7 +79,74 @@ static int build_lattice(int kind, lattice_t* L)
                 L->c[k][2] == -L->c[i][2])
                 L->opp[i] = k;
     }
+    build_mrt_basis(L);
     return L->q;
+}
+
+/* MRT moment basis (Sec. 2.1, Eq. 20).  The paper names no basis; the one
+ * used here is the Gram-Schmidt orthogonalisation, under the weighted inner
+ * product <a, b> = sum_i w_i a_i b_i, of the monomials c_x^a c_y^b c_z^c
+ * (a, b, c <= 2) taken in order of degree, with |c|^2 first among the
+ * degree-2 ones; monomials that add nothing on the lattice are dropped.
+ * Groups: degree 0-1 conserved, the |c|^2 row bulk, the other degree-2 rows
+ * shear, odd degree >= 3 odd, even degree >= 4 even. */
+static void build_mrt_basis(lattice_t* L)
+{
+    int nrow = 0;
+    for (int deg = 0; deg <= 6; ++deg) {
+        /* candidate monomials of this degree; at degree 2 the trace first */
+        int cand[32][3], nc = 0;
+        if (deg == 2) { cand[nc][0] = -1; nc++; }
+        for (int a = 0; a <= 2; ++a)
+            for (int b = 0; b <= 2; ++b)
+                for (int cc = 0; cc <= 2; ++cc)
+                    if (a + b + cc == deg) { cand[nc][0] = a; cand[nc][1] = b; cand[nc][2] = cc; nc++; }
+        int first_deg2 = 1;
+        for (int k = 0; k < nc; ++k) {
+            double v[QMAX];
+            for (int i = 0; i < L->q; ++i) {
+                if (cand[k][0] < 0) {
+                    v[i] = (double)(L->c[i][0] * L->c[i][0] + L->c[i][1] * L->c[i][1] + L->c[i][2] * L->c[i][2]);
+                } else {
+                    v[i] = 1.0;
+                    for (int e = 0; e < cand[k][0]; ++e) v[i] *= L->c[i][0];
+                    for (int e = 0; e < cand[k][1]; ++e) v[i] *= L->c[i][1];
+                    for (int e = 0; e < cand[k][2]; ++e) v[i] *= L->c[i][2];
+                }
+            }
+            double n0 = 0.0;
+            for (int i = 0; i < L->q; ++i) n0 += L->w[i] * v[i] * v[i];
+            for (int pass = 0; pass < 2; ++pass)
+                for (int r = 0; r < nrow; ++r) {
+                    double dot = 0.0;
+                    for (int i = 0; i < L->q; ++i) dot += L->w[i] * v[i] * L->mrt[r][i];
+                    for (int i = 0; i < L->q; ++i) v[i] -= dot / L->mrt_n[r] * L->mrt[r][i];
+                }
+            double n = 0.0;
+            for (int i = 0; i < L->q; ++i) n += L->w[i] * v[i] * v[i];
+            if (n <= 1e-12 * (n0 > 0.0 ? n0 : 1.0)) continue;
+            for (int i = 0; i < L->q; ++i) L->mrt[nrow][i] = v[i];
+            L->mrt_n[nrow] = n;
+            if (deg <= 1) L->mrt_group[nrow] = MRT_CONSERVED;
+            else if (deg == 2) { L->mrt_group[nrow] = first_deg2 ? MRT_BULK : MRT_SHEAR; first_deg2 = 0; }
+            else L->mrt_group[nrow] = (deg % 2) ? MRT_ODD : MRT_EVEN;
+            nrow++;
+        }
+    }
+}
+
+/* Omega = -M^{-1} S M (f - f_eq) (Eq. 20) with S from the group rates; with
+ * rows orthogonal under the weights, M^{-1} = W M^T N^{-1}, so
+ * (M^{-1} S M)_ij = sum_k s_k w_i m_k(i) m_k(j) / n_k. */
+static void mrt_apply(const lattice_t* L, const double rate[5], const double* fneq, double* out)
+{
+    for (int i = 0; i < L->q; ++i) out[i] = 0.0;
+    for (int k = 0; k < L->q; ++k) {
+        double mk = 0.0;
+        for (int j = 0; j < L->q; ++j) mk += L->mrt[k][j] * fneq[j];
+        const double sk = rate[L->mrt_group[k]] * mk / L->mrt_n[k];
+        for (int i = 0; i < L->q; ++i) out[i] += sk * L->w[i] * L->mrt[k][i];
+    }
 }
 
 int orc_lattice_info(int lattice, int* d, int* c, double* w, int* opp)
@@ -172,9 +247,26 @@ static void collide_pr(const lattice_t* L, const orc_rheology* rh, const double*
      * using the relaxation time of the previous step (explicit update,
      * Sec. 3).  Reading: Eq. 24 omits the density that Eq. 33 carries; the
      * density is kept (D = -Pi_neq / (2 rho cs^2 tau)). */
-    second_moment_of_difference(L, fbar, feq, Pneq);
-    for (int a = 0; a < 3; ++a)
-        for (int b = 0; b < 3; ++b) D[a][b] = -Pneq[a][b] / (2.0 * rho * CS2 * tau_prev);
+    const int mrt = rh->mrt_bulk > 0.0 || rh->mrt_even > 0.0;
+    double fneq[QMAX];
+    for (int i = 0; i < L->q; ++i) fneq[i] = fbar[i] - feq[i];
+    if (!mrt) {
+        second_moment_of_difference(L, fbar, feq, Pneq);
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) D[a][b] = -Pneq[a][b] / (2.0 * rho * CS2 * tau_prev);
+    } else {
+        /* Eq. 23: D from the second moment of M^{-1} S M (f - f_eq), with the
+         * shear rate of the previous step and the bulk rate as given. */
+        double rate[5] = {0.0, rh->mrt_bulk > 0.0 ? rh->mrt_bulk : 1.0 / tau_prev, 1.0 / tau_prev, 0.0, 0.0};
+        double g[QMAX];
+        mrt_apply(L, rate, fneq, g);
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) {
+                double s2 = 0.0;
+                for (int i = 0; i < L->q; ++i) s2 += L->c[i][a] * L->c[i][b] * g[i];
+                D[a][b] = -s2 / (2.0 * rho * CS2);
+            }
+    }
 
     /* Sec. 4.2.2: for a flow known to run along one axis, the normal
      * component of the strain rate along it (a Burnett-order artefact of the
@@ -198,15 +290,26 @@ static void collide_pr(const lattice_t* L, const orc_rheology* rh, const double*
     for (int a = 0; a < 3; ++a) ushift[a] = u[a] + rh->g[a];
     equilibrium(L, rho, ushift, feq_shift);
 
-    /* TRT: symmetric and antisymmetric parts under i <-> opposite(i). */
-    for (int i = 0; i < L->q; ++i) {
-        int k = L->opp[i];
-        double f_sym = 0.5 * (fbar[i] + fbar[k]);
-        double f_asym = 0.5 * (fbar[i] - fbar[k]);
-        double e_sym = 0.5 * (feq[i] + feq[k]);
-        double e_asym = 0.5 * (feq[i] - feq[k]);
-        double omega = -(f_sym - e_sym) / tau_even - (f_asym - e_asym) / tau_odd;
-        fpost[i] = fbar[i] + omega + (feq_shift[i] - feq[i]);
+    if (!mrt) {
+        /* TRT: symmetric and antisymmetric parts under i <-> opposite(i). */
+        for (int i = 0; i < L->q; ++i) {
+            int k = L->opp[i];
+            double f_sym = 0.5 * (fbar[i] + fbar[k]);
+            double f_asym = 0.5 * (fbar[i] - fbar[k]);
+            double e_sym = 0.5 * (feq[i] + feq[k]);
+            double e_asym = 0.5 * (feq[i] - feq[k]);
+            double omega = -(f_sym - e_sym) / tau_even - (f_asym - e_asym) / tau_odd;
+            fpost[i] = fbar[i] + omega + (feq_shift[i] - feq[i]);
+        }
+    } else {
+        /* MRT (Eq. 20): shear moments at 1/tau_even, odd moments at
+         * 1/tau_odd (the magic number), bulk and higher even moments at
+         * their own rates. */
+        double rate[5] = {0.0, rh->mrt_bulk > 0.0 ? rh->mrt_bulk : 1.0 / tau_even, 1.0 / tau_even,
+                          1.0 / tau_odd, rh->mrt_even > 0.0 ? rh->mrt_even : 1.0 / tau_even};
+        double om[QMAX];
+        mrt_apply(L, rate, fneq, om);
+        for (int i = 0; i < L->q; ++i) fpost[i] = fbar[i] - om[i] + (feq_shift[i] - feq[i]);
     }
 
     /* Stress magnitude sqrt(sigma:sigma/2) = rho nu_app gamma for

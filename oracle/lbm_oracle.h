@@ -46,6 +46,10 @@ typedef struct {
     double gamma_c;   /* strain-rate cut-off of the interpolation (PR)     */
     double lambda;    /* TRT magic number (PR)                             */
     double g[3];      /* body force per unit mass                          */
+    double mrt_bulk;  /* PR / PRI: MRT relaxation rates (Sec. 2.1, Eq. 20) of */
+    double mrt_even;  /* the bulk (trace) moment and of the even moments of  */
+                      /* order >= 4; 0 = the shear rate (TRT).  Odd moments   */
+                      /* keep the magic-number rate.  Both 0: plain TRT.      */
 } orc_rheology;
 
 typedef struct orc_domain orc_domain;

@@ -44,13 +44,16 @@ MUTATIONS = {
     "pri_bisection_flipped": ("        if (F > 0.0) hi = mid;\n        else lo = mid;", "        if (F > 0.0) lo = mid;\n        else hi = mid;"),
     "pri_bracket_without_density": ("double hi = 0.5 + (rh->nu_p + rh->m * rh->sigma_y / rho) / CS2;",
                                     "double hi = 0.5 + (rh->nu_p + rh->m * rh->sigma_y) / CS2 * 0.5;"),
+    "mrt_no_bulk_group": ("L->mrt_group[nrow] = first_deg2 ? MRT_BULK : MRT_SHEAR;", "L->mrt_group[nrow] = MRT_SHEAR;"),
+    "mrt_inverse_without_weights": ("for (int i = 0; i < L->q; ++i) out[i] += sk * L->w[i] * L->mrt[k][i];",
+                                    "for (int i = 0; i < L->q; ++i) out[i] += sk * L->mrt[k][i] / L->q;"),
     "flow_axis_pr_ignored": ("if (rh->flow_axis >= 1 && rh->flow_axis <= 3) D[rh->flow_axis - 1][rh->flow_axis - 1] = 0.0;",
                              "if (0) D[rh->flow_axis - 1][rh->flow_axis - 1] = 0.0;"),
 }
 
 PIN_TESTS = ["tests/test_oracle_lattice.py", "tests/test_oracle_operators.py",
              "tests/test_oracle_flows.py", "tests/test_oracle_residual.py", "tests/test_oracle_burnett.py",
-             "tests/test_oracle_pri.py"]
+             "tests/test_oracle_mrt.py", "tests/test_oracle_pri.py"]
 
 
 @pytest.mark.parametrize("name", sorted(MUTATIONS))

@@ -62,20 +62,21 @@ def test_equilibrium_node_takes_nu0(orc):
 
 
 def test_channel_steady_state_matches_explicit_and_reference(orc):
-    H, g, nu, m = 64, 1e-5, 0.1, 1e4
+    H, g, nu, m = 32, 2e-5, 0.1, 1e4
     sy = g * H / 4.0
     ux = {}
     for op in (orc.PR, orc.PRI):
         rh = orc.rheology(op, nu, sy, m, 1e-8, 0.25, (g, 0, 0))
-        dom = orc.Domain(0, (4, H, 1), (1, 0, 1), rh)
-        dom.step(40000)
+        dom = orc.Domain(0, (2, H, 1), (1, 0, 1), rh)
+        dom.step(20000)
         _, u, _, _ = dom.moments()
-        ux[op] = u[0].reshape(H, 4)
+        ux[op] = u[0].reshape(H, 2)
     import warnings
     with warnings.catch_warnings():
         warnings.simplefilter("ignore")
         ref = _channel_regularised(H, g, nu, sy, m)
-    assert np.max(np.abs(ux[orc.PRI] - ref[:, None])) < 1.5e-3 * ref.max()
+    # H = 32: the Lambda = 1/4 wall slip g/(24 nu) is ~1.2e-3 of the peak
+    assert np.max(np.abs(ux[orc.PRI] - ref[:, None])) < 3e-3 * ref.max()
     assert np.max(np.abs(ux[orc.PRI] - ux[orc.PR])) < 1e-6 * ref.max()
 
 
