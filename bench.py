@@ -270,8 +270,8 @@ def main():
                     help="run a 1 GiB device copy first (counter calibration under rocprofv3)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only; multi-GPU scaling is not part of it "
-              "(see DESIGN.md for how the domain would shard)", file=sys.stderr)
+        print("bench.py: runs on one GPU only; decomposing the domain over several GPUs "
+              "is not implemented", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -105,6 +105,17 @@ typedef struct {
                                 normal component (Sec. 4.2.2): PR leaves d_aa
                                 out of the strain rate, IR sets T_aa to zero
                                 before the deviator.  Other values: EINVAL. */
+    double mrt_bulk;         /* PR, PRI: MRT base collision (Sec. 2.1, Eqs. 20 */
+    double mrt_even;         /* and 23) instead of TRT.  Relaxation rates in
+                                (0, 2) of the bulk (trace) moment and of the
+                                even moments of order >= 4; 0 takes the shear
+                                rate 1/tau.  Both 0: TRT.  The moment basis
+                                is orthogonal under the lattice weights
+                                (shear and bulk parts of the second-order
+                                Hermite projection, the odd moments at the
+                                magic-number rate, the rest).  IR: must be 0;
+                                PRI: mrt_bulk must be 0.  Out of [0, 2):
+                                EINVAL. */
 } lbm_rheology;
 
 typedef struct {

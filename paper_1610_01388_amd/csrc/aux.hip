@@ -390,6 +390,12 @@ hipError_t launch_readout(int lat, int op, int prec, const NodeArgs& a, hipStrea
         else if (op == OP_PRI)
             hipLaunchKernelGGL((k_readout<decltype(L)::value, OP_PRI, decltype(P)::value>), dim3(nblk(a.count)),
                                dim3(256), 0, s, a);
+        else if (op == (OP_PR | OP_MRT))
+            hipLaunchKernelGGL((k_readout<decltype(L)::value, OP_PR | OP_MRT, decltype(P)::value>),
+                               dim3(nblk(a.count)), dim3(256), 0, s, a);
+        else if (op == (OP_PRI | OP_MRT))
+            hipLaunchKernelGGL((k_readout<decltype(L)::value, OP_PRI | OP_MRT, decltype(P)::value>),
+                               dim3(nblk(a.count)), dim3(256), 0, s, a);
         else
             hipLaunchKernelGGL((k_readout<decltype(L)::value, OP_IR, decltype(P)::value>), dim3(nblk(a.count)),
                                dim3(256), 0, s, a);
@@ -399,6 +405,7 @@ hipError_t launch_readout(int lat, int op, int prec, const NodeArgs& a, hipStrea
 
 hipError_t launch_init(int lat, int op, int prec, const NodeArgs& a, double rho, hipStream_t s)
 {
+    op = op_base(op);  // the initial state does not depend on the base collision
     return dispatch_lat_prec(lat, prec, [&](auto L, auto P) {
         if (op == OP_PR)
             hipLaunchKernelGGL((k_init<decltype(L)::value, OP_PR, decltype(P)::value>), dim3(nblk(a.N)), dim3(256),

@@ -103,6 +103,12 @@ int check_rheology(const lbm_rheology* r)
     if (r->fp16_scale_log2 < 0 || r->fp16_scale_log2 > 24) return fail(LBM_EINVAL, "fp16_scale_log2 outside 0..24");
     if (!(r->fallback_band >= 0)) return fail(LBM_EINVAL, "fallback_band must be >= 0");
     if (r->flow_axis < 0 || r->flow_axis > 3) return fail(LBM_EINVAL, "flow_axis must be 0 (off) or 1..3");
+    if (!(r->mrt_bulk >= 0 && r->mrt_bulk < 2) || !(r->mrt_even >= 0 && r->mrt_even < 2))
+        return fail(LBM_EINVAL, "MRT rates must lie in [0, 2) (0: the shear rate)");
+    if ((r->mrt_bulk > 0 || r->mrt_even > 0) && r->op == LBM_IR)
+        return fail(LBM_EINVAL, "the MRT base collision applies to the PR operators");
+    if (r->mrt_bulk > 0 && r->op == LBM_PRI)
+        return fail(LBM_EINVAL, "PRI takes no separate MRT bulk rate (its tau solve scales the whole strain rate)");
     return LBM_OK;
 }
 
@@ -224,7 +230,15 @@ Coll<C> make_coll(const lbm_rheology& r)
     c.pr_ec = (C)(-std::expm1(-r.m * gc) / gc);
     c.band = (C)r.fallback_band;
     c.axis = r.flow_axis;
+    c.mrt_b = (C)r.mrt_bulk;
+    c.mrt_e = (C)r.mrt_even;
     return c;
+}
+
+// Kernel operator code: the ABI operator plus the MRT flag.
+int kernel_op(const lbm_rheology& r)
+{
+    return r.op | ((r.mrt_bulk > 0 || r.mrt_even > 0) ? (int)OP_MRT : 0);
 }
 
 char* copy_ptr(lbm_domain* dm, int k) { return dm->pdf + (size_t)k * dm->L.pdf_copy; }
@@ -357,7 +371,7 @@ int run_steps(lbm_domain* dm, int64_t nsteps)
             a.dst = dm->pdf;
         }
         const bool mon = dm->mon_k > 0 && (dm->t % dm->mon_k) == 0;
-        HIPCHK(launch_step(dm->d.lattice, dm->r.op, dm->d.precision, pat, mon, dm->d.layout, a, dm->stream));
+        HIPCHK(launch_step(dm->d.lattice, kernel_op(dm->r), dm->d.precision, pat, mon, dm->d.layout, a, dm->stream));
         if (mon) {
             char* rec = dm->work + dm->L.hist + (size_t)(dm->hist_written % kHistory) * sizeof(MonitorRecord);
             // the compact AA local phase runs one block per 256 fluid slots, the others one per tile
@@ -623,7 +637,7 @@ int lbm_monitors(lbm_domain* dm, lbm_monitor* out)
     a.count = dm->N;
     a.reduce = 1;
     int64_t nb = 0;
-    HIPCHK(launch_readout(dm->d.lattice, dm->r.op, dm->d.precision, a, dm->stream, &nb));
+    HIPCHK(launch_readout(dm->d.lattice, kernel_op(dm->r), dm->d.precision, a, dm->stream, &nb));
     char* rec = dm->work + dm->L.rec;
     HIPCHK(launch_finalize((double*)dm->work, nb, rec, dm->t, (double)dm->N, dm->stream));
     HIPCHK(hipMemcpyAsync(out, rec, sizeof(MonitorRecord), hipMemcpyDeviceToHost, dm->stream));
@@ -657,7 +671,7 @@ int lbm_read_moments(lbm_domain* dm, double* rho, double* u, double* nu_app, uin
         a.out_flags = (uint8_t*)(stage + 5 * cnt);
         a.n0 = n0;
         a.count = cnt;
-        HIPCHK(launch_readout(dm->d.lattice, dm->r.op, dm->d.precision, a, dm->stream, nullptr));
+        HIPCHK(launch_readout(dm->d.lattice, kernel_op(dm->r), dm->d.precision, a, dm->stream, nullptr));
         if (rho) HIPCHK(hipMemcpyAsync(rho + n0, stage, cnt * 8, hipMemcpyDeviceToHost, dm->stream));
         if (u)
             for (int k = 0; k < 3; ++k)
@@ -1159,6 +1173,8 @@ int batch_validate(const lbm_desc* descs, const lbm_rheology* rh, int32_t count)
         if (descs[k].scheme != LBM_AA) return fail(LBM_EINVAL, "batches use the AA scheme");
         if (rh[k].op != LBM_PR && rh[k].op != LBM_IR)
             return fail(LBM_EINVAL, "simulation %d: batches take the PR and IR operators", k);
+        if (rh[k].mrt_bulk > 0 || rh[k].mrt_even > 0)
+            return fail(LBM_EINVAL, "simulation %d: batches use the TRT base collision (no MRT rates)", k);
         if ((int64_t)descs[k].nx * descs[k].ny * descs[k].nz * lattice_q(descs[k].lattice) >= ((int64_t)1 << 31))
             return fail(LBM_EINVAL, "simulation %d: batched simulations need Q * nodes < 2^31", k);
         if (rh[k].fp64_fallback != rh[0].fp64_fallback || rh[k].fp16_scale_log2 != rh[0].fp16_scale_log2)

@@ -18,11 +18,16 @@ namespace lbm {
 // (the strain rate uses the previous step's tau, kept per node); IR:
 // implicitly regularised; PRI: PR with the implicit update of Sec. 3 (the
 // tau consistent with its own strain rate, found per node; no state).
-enum { OP_PR = 0, OP_IR = 1, OP_PRI = 2 };
-// TRT + EDM with a Papanastasiou viscosity
-__host__ __device__ constexpr bool pr_family(int op) { return op != OP_IR; }
+// OP_MRT is a flag on PR and PRI: MRT base collision (Sec. 2.1) instead of
+// TRT, a separate kernel instantiation so that the TRT kernels do not carry
+// its registers.
+enum { OP_PR = 0, OP_IR = 1, OP_PRI = 2, OP_MRT = 4 };
+__host__ __device__ constexpr int op_base(int op) { return op & 3; }
+// TRT (or MRT) + EDM with a Papanastasiou viscosity
+__host__ __device__ constexpr bool pr_family(int op) { return op_base(op) != OP_IR; }
 // carries a relaxation-time field from step to step
-__host__ __device__ constexpr bool has_tau(int op) { return op == OP_PR; }
+__host__ __device__ constexpr bool has_tau(int op) { return op_base(op) == OP_PR; }
+__host__ __device__ constexpr bool is_mrt(int op) { return (op & OP_MRT) != 0; }
 
 __device__ __forceinline__ double d_sqrt(double v) { return sqrt(v); }
 __device__ __forceinline__ float d_sqrt(float v) { return sqrtf(v); }
@@ -38,6 +43,7 @@ template <class C> struct Coll {
     C pr_ec;      // PR: -expm1(-m gamma_c) / gamma_c  (nu_app at the cut-off is nu_p + sigma_y pr_ec / rho)
     C band;       // FP64 fallback band
     int axis;     // 0, or 1..3: known flow axis whose normal component the collision drops (Sec. 4.2.2)
+    C mrt_b, mrt_e;  // MRT rates of the bulk moment and of the even moments of order >= 4 (<= 0: shear rate)
 };
 
 template <class C> struct Moments {
@@ -172,7 +178,7 @@ __device__ __forceinline__ Pre<C> rheology(const Moments<C>& mo, const Coll<C>& 
         C t[6];
         noneq_second<LAT>(mo, r.rho, r.u, t);
         C tau_s = tau_prev;
-        if (OP == OP_PRI) {  // strain rate at tau = 1, then the self-consistent tau
+        if (op_base(OP) == OP_PRI) {  // strain rate at tau = 1, then the self-consistent tau
             const C c1 = C(-1.5) * irho;
             C d1[6];
 #pragma unroll
@@ -186,6 +192,18 @@ __device__ __forceinline__ Pre<C> rheology(const Moments<C>& mo, const Coll<C>& 
         C dd[6];
 #pragma unroll
         for (int a = 0; a < 6; ++a) dd[a] = coef * t[a];
+        if (is_mrt(OP) && p.mrt_b > C(0)) {
+            // Eq. 23 with MRT: the trace part relaxes at the bulk rate
+            const C trd = ((D == 3) ? t[0] + t[1] + t[2] : t[0] + t[1]) / C(D);
+            const C corr = C(-1.5) * irho * (p.mrt_b - C(1) / tau_s) * trd;
+            dd[0] += corr;
+            dd[1] += corr;
+            if (D == 3) dd[2] += corr;
+        }
+        if (is_mrt(OP)) {
+#pragma unroll
+            for (int a = 0; a < 6; ++a) r.a[a] = t[a];  // non-equilibrium second moment
+        }
         // known flow axis: its normal strain rate is a Burnett-order artefact
         if (p.axis == 1) dd[0] = C(0);
         if (p.axis == 2) dd[1] = C(0);
@@ -252,12 +270,26 @@ __device__ __forceinline__ void relax(C (&h)[Lattice<LAT>::Q], const Moments<C>&
     if (pr_family(OP)) {
         const C om_p = C(1) / r.tau_p;
         const C om_m = C(1) / r.tau_m;
+        // MRT (Sec. 2.1): with the weights' inner product the second-order
+        // Hermite projection of h - h_eq splits into shear (cc : Pi_dev) and
+        // bulk ((tr/d)(|c|^2 - d cs^2)) parts; the remaining even moments take
+        // om_e, the odd ones om_m:  even change = om_e n_s + (om_p - om_e) f2d
+        // + (om_b - om_e) f2b.  Without MRT, om_e = om_b = om_p (TRT).
+        constexpr bool mrt = is_mrt(OP);
+        const C om_e = (mrt && p.mrt_e > C(0)) ? p.mrt_e : om_p;
+        const C om_b = (mrt && p.mrt_b > C(0)) ? p.mrt_b : om_p;
+        constexpr int D = L::D;
+        const C* pn = r.a;
+        const C trd = ((D == 3) ? pn[0] + pn[1] + pn[2] : pn[0] + pn[1]) / C(D);
+        const C dsh = om_p - om_e, dbu = om_b - om_e;
         const C ug = p.g[0] * (C(2) * u[0] + p.g[0]) + p.g[1] * (C(2) * u[1] + p.g[1]) +
                      p.g[2] * (C(2) * u[2] + p.g[2]);
-        {  // rest velocity: symmetric only
+        {  // rest velocity: symmetric only (f2d = 0, f2b = -cs^2 d trd * 9/2 w = -1.5 w d trd)
             const C w = C(L::w[0]);
             const C es = w * (mo.drho - C(1.5) * r.rho * uu);
-            h[0] = h[0] - om_p * (h[0] - es) - C(1.5) * r.rho * w * ug;
+            C ns0 = om_e * (h[0] - es);
+            if (mrt) ns0 += dbu * (C(-1.5) * w * C(D) * trd);
+            h[0] = h[0] - ns0 - C(1.5) * r.rho * w * ug;
         }
 #pragma unroll
         for (int i = 1; i < L::Q; i += 2) {
@@ -274,7 +306,20 @@ __device__ __forceinline__ void relax(C (&h)[Lattice<LAT>::Q], const Moments<C>&
             const C ea = C(3) * w * r.rho * cu;
             const C hs = C(0.5) * (h[i] + h[k]);
             const C ha = C(0.5) * (h[i] - h[k]);
-            const C ns = om_p * (hs - es);
+            C ns = om_e * (hs - es);
+            if (mrt) {
+                C cpc = 0;  // c c : Pi_neq
+                add_c<LAT>(cpc, pn[0], L::cx[i] * L::cx[i]);
+                add_c<LAT>(cpc, pn[1], L::cy[i] * L::cy[i]);
+                add_c<LAT>(cpc, pn[2], L::cz[i] * L::cz[i]);
+                add_c<LAT>(cpc, C(2) * pn[3], L::cx[i] * L::cy[i]);
+                add_c<LAT>(cpc, C(2) * pn[4], L::cx[i] * L::cz[i]);
+                add_c<LAT>(cpc, C(2) * pn[5], L::cy[i] * L::cz[i]);
+                const int c2 = L::cx[i] * L::cx[i] + L::cy[i] * L::cy[i] + L::cz[i] * L::cz[i];
+                const C f2d = C(4.5) * w * (cpc - trd * C(c2));
+                const C f2b = C(4.5) * w * trd * (C(c2) - C(D) / C(3));
+                ns += dsh * f2d + dbu * f2b;
+            }
             const C na = om_m * (ha - ea);
             // f_eq(u+g) - f_eq(u) for +c and -c
             const C fs = r.rho * w * (C(4.5) * cg * (C(2) * cu + cg) - C(1.5) * ug);

@@ -497,7 +497,19 @@ hipError_t launch_step_lattice(int op, int prec, int pat, bool mon, int layout, 
         case PREC_F32: return go_pat<LAT, OP_PRI, PREC_F32>(pat, mon, layout, a, s);
         case PREC_F16: return go_pat<LAT, OP_PRI, PREC_F16>(pat, mon, layout, a, s);
         }
-    } else {
+    } else if (op == (OP_PR | OP_MRT)) {
+        switch (prec) {
+        case PREC_F64: return go_pat<LAT, OP_PR | OP_MRT, PREC_F64>(pat, mon, layout, a, s);
+        case PREC_F32: return go_pat<LAT, OP_PR | OP_MRT, PREC_F32>(pat, mon, layout, a, s);
+        case PREC_F16: return go_pat<LAT, OP_PR | OP_MRT, PREC_F16>(pat, mon, layout, a, s);
+        }
+    } else if (op == (OP_PRI | OP_MRT)) {
+        switch (prec) {
+        case PREC_F64: return go_pat<LAT, OP_PRI | OP_MRT, PREC_F64>(pat, mon, layout, a, s);
+        case PREC_F32: return go_pat<LAT, OP_PRI | OP_MRT, PREC_F32>(pat, mon, layout, a, s);
+        case PREC_F16: return go_pat<LAT, OP_PRI | OP_MRT, PREC_F16>(pat, mon, layout, a, s);
+        }
+    } else if (op == OP_IR) {
         switch (prec) {
         case PREC_F64: return go_pat<LAT, OP_IR, PREC_F64>(pat, mon, layout, a, s);
         case PREC_F32: return go_pat<LAT, OP_IR, PREC_F32>(pat, mon, layout, a, s);

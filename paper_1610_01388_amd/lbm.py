@@ -43,7 +43,8 @@ class lbm_rheology(ctypes.Structure):
                 ("nu_p", ctypes.c_double), ("sigma_y", ctypes.c_double), ("rho0", ctypes.c_double),
                 ("m", ctypes.c_double), ("gamma_c", ctypes.c_double), ("lambda_trt", ctypes.c_double),
                 ("g", ctypes.c_double * 3), ("fallback_band", ctypes.c_double),
-                ("fp16_scale_log2", ctypes.c_int32), ("flow_axis", ctypes.c_int32)]
+                ("fp16_scale_log2", ctypes.c_int32), ("flow_axis", ctypes.c_int32),
+                ("mrt_bulk", ctypes.c_double), ("mrt_even", ctypes.c_double)]
 
 
 class lbm_monitor(ctypes.Structure):
@@ -317,7 +318,8 @@ def make_desc(lattice, dims, periodic, precision="FP64", scheme="AA", layout="CO
 
 
 def make_rheology(op, nu_p, sigma_y=0.0, m=0.0, g=(0.0, 0.0, 0.0), rho0=1.0, gamma_c=1e-8,
-                  lambda_trt=0.25, fp64_fallback=False, fallback_band=0.0, fp16_scale_log2=14, flow_axis=0):
+                  lambda_trt=0.25, fp64_fallback=False, fallback_band=0.0, fp16_scale_log2=14, flow_axis=0,
+                  mrt_bulk=0.0, mrt_even=0.0):
     r = lbm_rheology()
     r.op = OPERATORS[op] if isinstance(op, str) else int(op)
     r.fp64_fallback = int(bool(fp64_fallback))
@@ -328,6 +330,8 @@ def make_rheology(op, nu_p, sigma_y=0.0, m=0.0, g=(0.0, 0.0, 0.0), rho0=1.0, gam
     r.fallback_band = float(fallback_band)
     r.fp16_scale_log2 = int(fp16_scale_log2)
     r.flow_axis = int(flow_axis)
+    r.mrt_bulk = float(mrt_bulk)
+    r.mrt_even = float(mrt_even)
     return r
 
 

@@ -64,6 +64,10 @@ def _desc(**kw):
     ({}, dict(op="PR", lambda_trt=0.0)),
     ({}, dict(fp16_scale_log2=30)),
     ({}, dict(flow_axis=4)),
+    ({}, dict(op="PR", mrt_bulk=2.5)),
+    ({}, dict(op="PR", mrt_even=-0.1)),
+    ({}, dict(op="IR", mrt_even=1.2)),
+    ({}, dict(op="PRI", mrt_bulk=1.2)),
     ({}, dict(flow_axis=-1)),
     ({}, dict(fallback_band=-1.0)),
 ])
@@ -140,4 +144,11 @@ def test_implicit_pr_needs_no_tau_and_batches_reject_it():
     with pytest.raises(lbm.LbmError) as e:
         lbm.lbm_batch_query_sizes([lbm.make_desc("D3Q19", (8, 8, 4), (0, 0, 1), "FP32", "AA")],
                                   [lbm.make_rheology("PRI", 0.1, 1e-4, 1e4)])
+    assert e.value.code == -1
+
+
+def test_batches_reject_mrt():
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_batch_query_sizes([lbm.make_desc("D3Q19", (8, 8, 4), (0, 0, 1), "FP32", "AA")],
+                                  [lbm.make_rheology("PR", 0.1, 1e-4, 1e4, mrt_even=1.5)])
     assert e.value.code == -1

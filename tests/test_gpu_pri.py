@@ -1,5 +1,5 @@
 """GPU tests of the PR model with the implicit relaxation-time update of
-Sec. 3 (operator PRI; the next-row N3): FP64 parity with the oracle (which
+Sec. 3 (operator PRI): FP64 parity with the oracle (which
 finds the same root by bisection) on every lattice, both schemes and both
 layouts, with solids and ragged tiles; the reduced-precision bars; the
 Bingham channel steady state against explicit PR and the 1-D regularised
