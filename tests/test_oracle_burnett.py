@@ -10,7 +10,8 @@ Bingham square duct driven along z (H = 15, Bi = 0.4, nu_p = 0.0125):
   * PR at large m: without the correction the Burnett-order d_zz keeps the
     strain rate from vanishing in the plug, so nu_app saturates below its
     limit nu_p + m sigma_y / rho and no node counts as unyielded; with it the
-    plug reaches the limit exactly.
+    plug reaches the limit exactly; the same holds with the implicit
+    relaxation-time update of Sec. 3.
 """
 import numpy as np
 import pytest
@@ -36,11 +37,13 @@ def test_ir_transverse_currents_vanish_with_correction(orc):
     assert uy1.sum() > 0 and uy0.sum() > 0
 
 
+@pytest.mark.parametrize("op", ["PR", "PRI"])
 @pytest.mark.parametrize("m", [1e6, 1e9])
-def test_pr_plug_reaches_viscosity_limit_with_correction(orc, m):
+def test_pr_plug_reaches_viscosity_limit_with_correction(orc, m, op):
+    """Explicit and implicit (Sec. 3) relaxation-time updates alike."""
     nu_lim = NU + m * SY
-    _, u0, nu0, uy0 = _duct(orc, orc.PR, m, 0)
-    _, u1, nu1, uy1 = _duct(orc, orc.PR, m, 3)
+    _, u0, nu0, uy0 = _duct(orc, getattr(orc, op), m, 0)
+    _, u1, nu1, uy1 = _duct(orc, getattr(orc, op), m, 3)
     assert abs(nu1.max() - nu_lim) <= 1e-9 * nu_lim
     assert nu0.max() < (1.0 - 1e-3) * nu_lim
     assert uy1.sum() > 0

@@ -47,8 +47,10 @@ MUTATIONS = {
     "mrt_no_bulk_group": ("L->mrt_group[nrow] = first_deg2 ? MRT_BULK : MRT_SHEAR;", "L->mrt_group[nrow] = MRT_SHEAR;"),
     "mrt_inverse_without_weights": ("for (int i = 0; i < L->q; ++i) out[i] += sk * L->w[i] * L->mrt[k][i];",
                                     "for (int i = 0; i < L->q; ++i) out[i] += sk * L->mrt[k][i] / L->q;"),
-    "flow_axis_pr_ignored": ("if (rh->flow_axis >= 1 && rh->flow_axis <= 3) D[rh->flow_axis - 1][rh->flow_axis - 1] = 0.0;",
-                             "if (0) D[rh->flow_axis - 1][rh->flow_axis - 1] = 0.0;"),
+    "flow_axis_pr_ignored": ("can be set to zero. */\n    if (rh->flow_axis >= 1 && rh->flow_axis <= 3) D[rh->flow_axis - 1]",
+                             "can be set to zero. */\n    if (0) D[rh->flow_axis - 1]"),
+    "flow_axis_pri_ignored": ("(2.0 * rho * CS2);\n    if (rh->flow_axis >= 1 && rh->flow_axis <= 3) D[rh->flow_axis - 1]",
+                              "(2.0 * rho * CS2);\n    if (0) D[rh->flow_axis - 1]"),
 }
 
 PIN_TESTS = ["tests/test_oracle_lattice.py", "tests/test_oracle_operators.py",
