@@ -339,7 +339,7 @@ static void collide_ir(const lattice_t* L, const orc_rheology* rh, const double*
     density_momentum(L, fbar, &rho, j);
     for (int a = 0; a < 3; ++a) F[a] = rho * rh->g[a];
 
-    /* Reading: f_eq is taken "half a step back", i.e. Phi/2 is subtracted
+    /* Reading: f_eq is taken half a time step back, i.e. Phi/2 is subtracted
      * from Eq. 12.  The velocity inside f_eq is (j + F/2)/rho so that the
      * post-collision momentum is j + F. */
     for (int a = 0; a < 3; ++a) u[a] = (j[a] + 0.5 * F[a]) / rho;

@@ -118,9 +118,10 @@ __device__ __forceinline__ C frob2(const C (&t)[6])
 // PRI: the relaxation time tau with tau = 1/2 + 3 nu_app(G / tau), G being
 // the strain rate Eq. 24 gives at tau = 1.  F(tau) = tau - 1/2 - 3 nu_app(G /
 // tau) is convex in tau and changes sign once on [1/2 + 3 nu_p, 1/2 + 3
-// nu_0]; Newton's method from the upper end, kept inside the shrinking
-// bracket (bisection whenever a step would leave it), stops when a step is
-// below the precision's resolution.
+// nu_0]; Newton's method, kept inside the shrinking bracket (bisection
+// whenever a step would leave it), stops when a step is below the
+// precision's resolution.  It starts at the root of the yielded asymptote
+// when that lies in the bracket, else at the upper end.
 template <class C>
 __device__ __forceinline__ C implicit_tau(C G, const Coll<C>& p, C irho)
 {
@@ -129,7 +130,11 @@ __device__ __forceinline__ C implicit_tau(C G, const Coll<C>& p, C irho)
     const C nuc = p.nu_p + s * p.pr_ec;
     C lo = C(0.5) + C(3) * p.nu_p;
     C hi = C(0.5) + C(3) * nu0;
+    // Start: where the root lies once m gamma is large (yielded node,
+    // nu_app ~ nu_p + s tau / G, linear in tau), else the upper end.
+    const C r = C(3) * s;
     C x = hi;
+    if (r < G) x = fmin(fmax(lo * G / (G - r), lo), hi);
     const C tol = sizeof(C) == 8 ? C(1e-14) : C(2e-7);
     for (int it = 0; it < 64; ++it) {
         const C gam = G / x;
@@ -146,9 +151,14 @@ __device__ __forceinline__ C implicit_tau(C G, const Coll<C>& p, C irho)
         if (F > C(0)) hi = x;
         else lo = x;
         const C dF = C(1) + C(3) * dnu * G / (x * x);
-        C xn = x - F / dF;
-        if (!(xn > lo && xn < hi)) xn = C(0.5) * (lo + hi);
-        const bool done = fabs(xn - x) <= tol * x || hi - lo <= tol * hi;
+        const C step = F / dF;
+        C xn = x - step;
+        // A step within tolerance ends the search before the bracket test:
+        // at an exact root (F = 0) x has just become a bracket end, and the
+        // strict test would send the next iterate off to the midpoint.
+        const bool conv = fabs(step) <= tol * x;
+        if (!conv && !(xn > lo && xn < hi)) xn = C(0.5) * (lo + hi);
+        const bool done = conv || hi - lo <= tol * hi;
         x = xn;
         if (done) break;
     }

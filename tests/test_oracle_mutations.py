@@ -56,6 +56,16 @@ MUTATIONS = {
 PIN_TESTS = ["tests/test_oracle_lattice.py", "tests/test_oracle_operators.py",
              "tests/test_oracle_flows.py", "tests/test_oracle_residual.py", "tests/test_oracle_burnett.py",
              "tests/test_oracle_mrt.py", "tests/test_oracle_pri.py"]
+# The pin file aimed at a mutation's area runs first (all files still run
+# until one fails), so that the suite does not spend minutes on flow pins
+# before reaching the one that targets the mistake.
+FIRST = {"residual_": "tests/test_oracle_residual.py", "flow_axis_": "tests/test_oracle_burnett.py",
+         "pri_": "tests/test_oracle_pri.py", "mrt_": "tests/test_oracle_mrt.py"}
+
+
+def _pin_order(name):
+    first = [f for pre, f in FIRST.items() if name.startswith(pre)]
+    return first + [f for f in PIN_TESTS if f not in first]
 
 
 @pytest.mark.parametrize("name", sorted(MUTATIONS))
@@ -71,6 +81,6 @@ def test_pins_reject_planted_mistake(name, tmp_path):
                            str(mutated), "-o", str(so), "-lm"])
     env = dict(os.environ, LBM_ORACLE_LIB=str(so))
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                        *PIN_TESTS], cwd=ROOT, env=env, capture_output=True, text=True,
+                        *_pin_order(name)], cwd=ROOT, env=env, capture_output=True, text=True,
                        timeout=600)
     assert r.returncode != 0, f"pins did not catch mutation {name}:\n{r.stdout[-2000:]}"
