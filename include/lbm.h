@@ -77,6 +77,15 @@ typedef enum { LBM_AB = 0, LBM_AA = 1 } lbm_scheme;
  * fluid data only.  DENSE: a slot for every node, one mask byte per node
  * staged in LDS tiles.  Both give identical results. */
 typedef enum { LBM_COMPACT = 0, LBM_DENSE = 1 } lbm_layout;
+/* Kernel of the compact layout's neighbour phases (the AA step that reads
+ * and writes neighbours' slots, and every A/B step).  ROWS runs one
+ * wavefront per 64-node row segment over the tiles of lbm_set_tile (lanes
+ * of solid nodes idle; fastest when most nodes are fluid).  SLOTS runs one
+ * thread per fluid slot, 64 consecutive slots per wavefront (every lane
+ * busy; fastest when most nodes are solid).  AUTO (default) takes SLOTS
+ * when fewer than 45% of the nodes are fluid, else ROWS.  Identical
+ * results. */
+typedef enum { LBM_PULL_AUTO = 0, LBM_PULL_SLOTS = 1, LBM_PULL_ROWS = 2 } lbm_pull_form;
 
 typedef struct {
     int32_t lattice;     /* lbm_lattice                                      */
@@ -238,8 +247,16 @@ int lbm_get_tile(lbm_domain* dom, int32_t* tx, int32_t* ty, int32_t* tz);
  * reports the values in effect. */
 int lbm_set_tile_order(lbm_domain* dom, int32_t brick_rows, int32_t brick_planes);
 int lbm_get_tile_order(lbm_domain* dom, int32_t* brick_rows, int32_t* brick_planes);
-/* Time candidate tile shapes on the bound buffers (the state is saved and
- * restored around the trial steps) and keep the fastest; synchronises. */
+/* Select the compact layout's neighbour-phase kernel (lbm_pull_form); tiles
+ * and tile order apply to ROWS only.  LBM_EINVAL for another value.  The
+ * dense layout ignores the setting.  Timing only, never results.  The
+ * getter reports the kernel in effect (SLOTS or ROWS; AUTO resolved with
+ * the current mask). */
+int lbm_set_pull_form(lbm_domain* dom, int32_t form);
+int lbm_get_pull_form(lbm_domain* dom, int32_t* form);
+/* Time candidate tile shapes (compact layout: and both neighbour-phase
+ * kernels) on the bound buffers (the state is saved and restored around the
+ * trial steps) and keep the fastest; synchronises. */
 int lbm_autotune(lbm_domain* dom, int32_t trial_steps);
 
 int lbm_destroy(lbm_domain* dom);

@@ -87,7 +87,7 @@ int64_t compact_stride(int64_t nf, int prec)
 
 struct Layout {
     size_t pdf_copy, pdf, tau, mask, part, hist, rec, uprev, stage, work;
-    size_t bits_off, base_off, mask_compact;  // compact mask: bitmap then word bases
+    size_t bits_off, base_off, wstart_off, mask_compact;  // compact mask: bitmap, word bases, group words
     int64_t max_parts, npad;
     int W;
 };
@@ -144,7 +144,8 @@ Layout layout_of(const lbm_desc* d, const lbm_rheology* r)
     const size_t words = (size_t)L.W * d->ny * d->nz;
     L.bits_off = 0;
     L.base_off = align_up(words * 8);
-    L.mask_compact = L.base_off + align_up(words * 4);
+    L.wstart_off = L.base_off + align_up(words * 4);
+    L.mask_compact = L.wstart_off + align_up(((size_t)N / 64 + 1) * 4);
     L.mask = std::max(align_up((size_t)N), L.mask_compact);
     L.max_parts = N / 32 + 64;
     L.part = 0;
@@ -177,6 +178,7 @@ struct lbm_domain {
     int64_t t = 0;
     int tx = 64, ty = 4, tz = 1;
     int bry = 0, brz = 0;  // tile-order bricks (0 = default for the tile shape)
+    int pull_form = LBM_PULL_AUTO;  // compact neighbour phases: slot or row-segment kernel
     int mon_k = 0;
     int64_t hist_written = 0, hist_read = 0;
     double umax_limit = 0.1;
@@ -202,6 +204,18 @@ int check_tile(const lbm_domain* dm, int tx, int ty, int tz)
     if (ntiles_of(dm, tx, ty, tz) > dm->L.max_parts)
         return fail(LBM_EINVAL, "tile %dx%dx%d leaves too many mostly empty tiles for this domain", tx, ty, tz);
     return LBM_OK;
+}
+
+// Neighbour-phase kernel in effect for the compact layout: the slot kernel
+// keeps every lane busy, the row-segment kernel reads the bitmap through the
+// scalar cache but idles the lanes of solid nodes; measured on D3Q27 FP64
+// 256^3 boxes, the row kernel leads from 70% fluid up and the slot kernel
+// below 40% (1.7x at 15%).
+bool pull_slots(const lbm_domain* dm)
+{
+    if (dm->d.layout != LBM_COMPACT) return false;
+    if (dm->pull_form == LBM_PULL_AUTO) return (double)dm->Nf < 0.45 * (double)dm->N;
+    return dm->pull_form == LBM_PULL_SLOTS;
 }
 
 int pow2ceil(int v)
@@ -316,9 +330,14 @@ StepArgs step_args(lbm_domain* dm)
     a.mask = dm->mask;
     a.bits = (const uint64_t*)(dm->mask + dm->L.bits_off);
     a.wbase = (const uint32_t*)(dm->mask + dm->L.base_off);
+    a.wstart = (const uint32_t*)(dm->mask + dm->L.wstart_off);
     a.W = dm->L.W;
     a.S = dm->S;
     a.nfluid = dm->Nf;
+    a.ngroups = (dm->Nf + 63) / 64;
+    a.nwords = (int64_t)dm->L.W * dm->d.ny * dm->d.nz;
+    a.slot_bpx = (int)(((dm->Nf + 255) / 256 + 7) / 8);
+    a.pull_slots = pull_slots(dm) ? 1 : 0;
     a.partials = (double*)dm->work;
     a.uprev = (double*)(dm->work + dm->L.uprev);
     a.N = dm->N;
@@ -393,9 +412,10 @@ int run_steps(lbm_domain* dm, int64_t nsteps)
         HIPCHK(launch_step(dm->d.lattice, kernel_op(dm->r), dm->d.precision, pat, mon, dm->d.layout, a, dm->stream));
         if (mon) {
             char* rec = dm->work + dm->L.hist + (size_t)(dm->hist_written % kHistory) * sizeof(MonitorRecord);
-            // the compact AA local phase runs one block per 256 fluid slots, the others one per tile
-            const int64_t nparts = (dm->d.layout == LBM_COMPACT && pat == PAT_AA_LOCAL) ? (dm->Nf + 255) / 256
-                                                                                          : a.ntiles;
+            // the compact slot kernels run one block per 256 fluid slots, the others one per tile
+            const int64_t nparts = (dm->d.layout == LBM_COMPACT && (pat == PAT_AA_LOCAL || a.pull_slots))
+                                       ? (dm->Nf + 255) / 256
+                                       : a.ntiles;
             HIPCHK(launch_finalize((double*)dm->work, nparts, rec, dm->t, (double)dm->N, dm->stream));
             dm->hist_written++;
         }
@@ -428,6 +448,8 @@ int upload_mask(lbm_domain* dm, const uint8_t* host_mask)
     const int64_t rows = (int64_t)dm->d.ny * dm->d.nz;
     std::vector<uint64_t> bits((size_t)rows * W, 0);
     std::vector<uint32_t> base((size_t)rows * W, 0);
+    std::vector<uint32_t> wstart;  // word holding slot 64 g
+    wstart.reserve((size_t)(dm->N / 64 + 1));
     uint64_t count = 0;
     for (int64_t r = 0; r < rows; ++r) {
         for (int w = 0; w < W; ++w) {
@@ -440,12 +462,16 @@ int upload_mask(lbm_domain* dm, const uint8_t* host_mask)
             base[(size_t)r * W + w] = (uint32_t)count;
             count += (uint64_t)__builtin_popcountll(word);
             if (count > 0xFFFFFFFFull) return fail(LBM_EINVAL, "compact layout holds at most 2^32-1 fluid nodes");
+            while ((uint64_t)wstart.size() * 64 < count) wstart.push_back((uint32_t)(r * W + w));
         }
     }
     dm->Nf = (int64_t)count;
     dm->S = compact_stride(dm->Nf, dm->d.precision);
     HIPCHK(hipMemcpyAsync(dm->mask + dm->L.bits_off, bits.data(), bits.size() * 8, hipMemcpyHostToDevice, dm->stream));
     HIPCHK(hipMemcpyAsync(dm->mask + dm->L.base_off, base.data(), base.size() * 4, hipMemcpyHostToDevice, dm->stream));
+    if (!wstart.empty())
+        HIPCHK(hipMemcpyAsync(dm->mask + dm->L.wstart_off, wstart.data(), wstart.size() * 4, hipMemcpyHostToDevice,
+                              dm->stream));
     HIPCHK(hipStreamSynchronize(dm->stream));
     return LBM_OK;
 }
@@ -838,6 +864,22 @@ int lbm_get_tile_order(lbm_domain* dm, int32_t* brick_rows, int32_t* brick_plane
     return LBM_OK;
 }
 
+int lbm_set_pull_form(lbm_domain* dm, int32_t form)
+{
+    if (!dm) return fail(LBM_EINVAL, "domain is NULL");
+    if (form != LBM_PULL_AUTO && form != LBM_PULL_SLOTS && form != LBM_PULL_ROWS)
+        return fail(LBM_EINVAL, "unknown pull form %d", (int)form);
+    dm->pull_form = form;
+    return LBM_OK;
+}
+
+int lbm_get_pull_form(lbm_domain* dm, int32_t* form)
+{
+    if (!dm || !form) return fail(LBM_EINVAL, "NULL argument");
+    *form = pull_slots(dm) ? LBM_PULL_SLOTS : LBM_PULL_ROWS;
+    return LBM_OK;
+}
+
 int lbm_get_tile(lbm_domain* dm, int32_t* tx, int32_t* ty, int32_t* tz)
 {
     if (!dm || !tx || !ty || !tz) return fail(LBM_EINVAL, "NULL argument");
@@ -879,16 +921,20 @@ int lbm_autotune(lbm_domain* dm, int32_t trial_steps)
         cand = dm->D == 3 ? cand3 : cand2;
         nc = dm->D == 3 ? (int)(sizeof cand3 / sizeof cand3[0]) : (int)(sizeof cand2 / sizeof cand2[0]);
     }
-    int best = -1;
+    int best = -2;  // -1: the slot kernel (compact layout), c >= 0: row kernel with tile c
     float best_ms = 1e30f;
     const int keep[3] = {dm->tx, dm->ty, dm->tz};
-    for (int c = 0; c < nc; ++c) {
-        const int tx = cand[c][0], ty = cand[c][1], tz = cand[c][2];
-        if (check_tile(dm, tx, ty, tz) != LBM_OK) continue;
-        if (tx > 2 * pow2ceil(dm->d.nx) || ty > 2 * pow2ceil(dm->d.ny)) continue;
-        dm->tx = tx;
-        dm->ty = ty;
-        dm->tz = tz;
+    const int keep_form = dm->pull_form;
+    for (int c = dm->d.layout == LBM_COMPACT ? -1 : 0; c < nc; ++c) {
+        if (c >= 0) {
+            const int tx = cand[c][0], ty = cand[c][1], tz = cand[c][2];
+            if (check_tile(dm, tx, ty, tz) != LBM_OK) continue;
+            if (tx > 2 * pow2ceil(dm->d.nx) || ty > 2 * pow2ceil(dm->d.ny)) continue;
+            dm->tx = tx;
+            dm->ty = ty;
+            dm->tz = tz;
+        }
+        dm->pull_form = c < 0 ? LBM_PULL_SLOTS : LBM_PULL_ROWS;
         if ((rc = run_steps(dm, 2))) break;
         HIPCHK(hipEventRecord(e0, dm->stream));
         if ((rc = run_steps(dm, trial_steps))) break;
@@ -904,15 +950,16 @@ int lbm_autotune(lbm_domain* dm, int32_t trial_steps)
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     dm->mon_k = mon_k;
+    dm->tx = keep[0];
+    dm->ty = keep[1];
+    dm->tz = keep[2];
+    dm->pull_form = keep_form;
     if (best >= 0) {
         dm->tx = cand[best][0];
         dm->ty = cand[best][1];
         dm->tz = cand[best][2];
-    } else {
-        dm->tx = keep[0];
-        dm->ty = keep[1];
-        dm->tz = keep[2];
     }
+    if (best >= -1 && dm->d.layout == LBM_COMPACT) dm->pull_form = best < 0 ? LBM_PULL_SLOTS : LBM_PULL_ROWS;
     const int rc_load = lbm_load(dm, saved.data(), bytes);
     if (rc) return rc;
     return rc_load;

@@ -38,11 +38,13 @@ __host__ __device__ constexpr bool mp_is_max(int k) { return k == MP_UMAX || k =
 //                  solid mask as one byte per node.
 //  LAYOUT_COMPACT: only fluid nodes have slots, numbered in node order
 //                  (x fastest); slot (i, k) at i*S + k with S = fluid count
-//                  rounded up to 64.  The mask is a bitmap per row (y, z):
-//                  W = ceil(nx/64) 64-bit words per row, bit x%64 of word
-//                  x/64 set for fluid, and wbase[row][word] = compact index
-//                  of the first fluid node at or after x = 64*word, so
-//                  k(x) = wbase + popcount(bits below x).
+//                  rounded up to 64 and padded off multiples of 64 KiB.
+//                  The mask is a bitmap per row (y, z): W = ceil(nx/64)
+//                  64-bit words per row, bit x%64 of word x/64 set for
+//                  fluid, and wbase[row][word] = compact index of the first
+//                  fluid node at or after x = 64*word, so k(x) = wbase +
+//                  popcount(bits below x).  wstart[g] names the word holding
+//                  slot 64 g (the slot kernels start their search there).
 enum { LAYOUT_COMPACT = 0, LAYOUT_DENSE = 1 };  // same values as lbm_layout
 
 struct StepArgs {
@@ -52,12 +54,17 @@ struct StepArgs {
     const uint8_t* mask;   // dense: 1 = solid
     const uint64_t* bits;  // compact: fluid bitmap [row][W]
     const uint32_t* wbase; // compact: [row][W]
-    double* partials;      // MON: MP_COUNT doubles per tile
+    const uint32_t* wstart; // compact: per group of 64 slots, the word [row][W] holding its first slot
+    double* partials;      // MON: MP_COUNT doubles per tile (slot kernels: per block)
     double* uprev;         // MON: output velocity of the previous fused monitor, [3][S]; overwritten
     int64_t N;             // nodes
     int64_t S;             // direction stride of the population arrays
     int64_t nfluid;        // fluid nodes (compact: slots 0 .. nfluid-1 are used)
+    int64_t ngroups;       // compact: ceil(nfluid / 64), entries of wstart
+    int64_t nwords;        // compact: W * ny * nz
     int W;                 // compact: words per row
+    int slot_bpx;          // slot kernels: ceil(ceil(nfluid / 256) / 8), blocks per XCD
+    int pull_slots;        // compact neighbour phases: 1 slot kernel, 0 row-segment kernel
     int nx, ny, nz;
     int per[3];
     int tx, ty, tz;        // tile shape (threads per block = tx*ty*tz)

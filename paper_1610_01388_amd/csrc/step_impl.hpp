@@ -442,6 +442,178 @@ __global__ __launch_bounds__(256) void k_local_slots(const StepArgs a)
         monitor_block<C>(active, mo, pr, cp, used_fb, a.partials + (int64_t)blockIdx.x * MP_COUNT, a.uprev, k, St);
 }
 
+// Position of the set bit of v with r set bits below it (r < popcount(v)).
+__device__ __forceinline__ int select_bit(uint64_t v, uint32_t r)
+{
+    int pos = 0;
+    uint32_t c = (uint32_t)__popc((uint32_t)v);
+    if (r >= c) { r -= c; pos = 32; v >>= 32; }
+    c = (uint32_t)__popc((uint32_t)v & 0xFFFFu);
+    if (r >= c) { r -= c; pos += 16; v >>= 16; }
+    c = (uint32_t)__popc((uint32_t)v & 0xFFu);
+    if (r >= c) { r -= c; pos += 8; v >>= 8; }
+    c = (uint32_t)__popc((uint32_t)v & 0xFu);
+    if (r >= c) { r -= c; pos += 4; v >>= 4; }
+    c = (uint32_t)__popc((uint32_t)v & 0x3u);
+    if (r >= c) { r -= c; pos += 2; v >>= 2; }
+    if (r >= (uint32_t)(v & 1u)) pos += 1;
+    return pos;
+}
+
+// Compact layout, neighbour phases (AA pull, A/B) with one thread per fluid
+// slot: a wavefront is 64 consecutive slots, so every lane is busy and the
+// runs start on 64-slot boundaries whatever the solid pattern (the
+// row-segment kernel above leaves the lanes of solid nodes idle and cuts the
+// runs where the rows' fluid counts fall).  Each lane finds its word by a
+// binary search between the words of its group's first slot and of the next
+// group's, its x by selecting the bit, and the slots of its 26 neighbours by
+// rank in the 9 neighbouring rows; slots of one row are consecutive, so
+// x - 1 and x + 1 are the rank -1 / +1 neighbours except across the
+// periodic x boundary.  Blocks go to the XCDs as 8 contiguous slot ranges.
+template <int LAT, int OP, int PREC, int PAT, bool MON>
+__global__ __launch_bounds__(256) void k_pull_slots(const StepArgs a)
+{
+    using L = Lattice<LAT>;
+    constexpr int Q = L::Q;
+    constexpr int D = L::D;
+    using S = typename Store<PREC>::S;
+    using C = typename Store<PREC>::C;
+    using T = typename Store<PREC>::T;
+    static_assert(PAT == PAT_AB || PAT == PAT_AA_PULL, "neighbour phases only");
+
+    const int64_t nblk = (a.nfluid + 255) >> 8;
+    const int b = blockIdx.x;
+    const int64_t cb = (int64_t)(b & 7) * a.slot_bpx + (b >> 3);
+    if (cb >= nblk) return;  // whole block leaves together
+    const int64_t k = cb * 256 + threadIdx.x;
+    const bool active = k < a.nfluid;
+    const int64_t St = a.S;
+
+    // nbf: fluid flag of x + d, bit (dx+1) + 3 r with r = (dy+1) + 3 (dz+1);
+    // im[r]: slot of x in row r (x itself if fluid, else the next fluid
+    // node); wr[r]: slot of the periodic image across the x boundary
+    // (node nx-1 for x = 0, node 0 for x = nx-1).
+    uint32_t nbf = 0;
+    uint32_t im[9], wr[9];
+#pragma unroll
+    for (int r = 0; r < 9; ++r) im[r] = wr[r] = 0;
+    int x = 0;
+    if (active) {
+        uint32_t lo = a.wstart[k >> 6];
+        uint32_t hi = ((k >> 6) + 1 < a.ngroups) ? a.wstart[(k >> 6) + 1] : (uint32_t)(a.nwords - 1);
+        while (lo < hi) {  // last word whose base is <= k: the one holding slot k
+            const uint32_t mid = (lo + hi + 1) >> 1;
+            if ((int64_t)a.wbase[mid] <= k) lo = mid;
+            else hi = mid - 1;
+        }
+        const uint32_t row = lo / (uint32_t)a.W;
+        const int wx = (int)(lo - row * (uint32_t)a.W);
+        const int bp = select_bit(a.bits[lo], (uint32_t)(k - (int64_t)a.wbase[lo]));
+        x = wx * 64 + bp;
+        const int y = (int)(row % (uint32_t)a.ny);
+        const int z = (int)(row / (uint32_t)a.ny);
+        const uint64_t below = (1ull << bp) - 1ull;
+        const int wl = (a.nx - 1) >> 6, bl = (a.nx - 1) & 63;  // last node of a row
+#pragma unroll
+        for (int dz = -1; dz <= 1; ++dz) {
+            if (D == 2 && dz != 0) continue;
+#pragma unroll
+            for (int dy = -1; dy <= 1; ++dy) {
+                int yy = y + dy, zz = z + dz;
+                bool rv = true;
+                if (yy < 0 || yy >= a.ny) {
+                    if (a.per[1]) yy = (yy + a.ny) % a.ny;
+                    else rv = false;
+                }
+                if (zz < 0 || zz >= a.nz) {
+                    if (a.per[2]) zz = (zz + a.nz) % a.nz;
+                    else rv = false;
+                }
+                if (!rv) continue;
+                const int r = (dy + 1) + 3 * (dz + 1);
+                const int64_t rw = ((int64_t)yy + (int64_t)a.ny * zz) * a.W;
+                const uint64_t word = a.bits[rw + wx];
+                bool fL = false, fR = false;
+                uint32_t wrap = 0;
+                if (bp > 0) fL = (word >> (bp - 1)) & 1;
+                else if (x > 0) fL = a.bits[rw + wx - 1] >> 63;
+                else if (a.per[0]) {
+                    const uint64_t lw = a.bits[rw + wl];
+                    fL = (lw >> bl) & 1;
+                    wrap = a.wbase[rw + wl] + (uint32_t)__popcll(lw & ((1ull << bl) - 1ull));
+                }
+                if (x + 1 < a.nx) fR = (bp < 63) ? ((word >> (bp + 1)) & 1) : (a.bits[rw + wx + 1] & 1);
+                else if (a.per[0]) {
+                    fR = a.bits[rw] & 1;
+                    if (x > 0) wrap = a.wbase[rw];  // nx = 1: the left image above is this node
+                }
+                nbf |= (fL ? 1u : 0u) << (3 * r + 0);
+                nbf |= (uint32_t)((word >> bp) & 1) << (3 * r + 1);
+                nbf |= (fR ? 1u : 0u) << (3 * r + 2);
+                im[r] = a.wbase[rw + wx] + (uint32_t)__popcll(word & below);
+                wr[r] = wrap;
+            }
+        }
+    }
+    // slot of the neighbour x + (dx, row r) (valid when it is fluid)
+    auto nbi = [&](int dx, int r) -> uint32_t {
+        if (dx == 0) return im[r];
+        if (dx < 0) return x > 0 ? im[r] - 1u : wr[r];
+        return x + 1 < a.nx ? im[r] + ((nbf >> (3 * r + 1)) & 1u) : wr[r];
+    };
+
+    C h[Q];
+    C tau_prev = C(0);
+    const Coll<C>& cp = coll_of<C>(a);
+    Moments<C> mo;
+    Pre<C> pr;
+    bool used_fb = false;
+    if (active) {
+        const S* A = (const S*)a.src;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const int r = (1 - L::cy[i]) + 3 * (1 - L::cz[i]);  // row of x - c_i
+            const bool fl = (nbf >> (3 * r + 1 - L::cx[i])) & 1;
+            int64_t idx;
+            if constexpr (PAT == PAT_AB)
+                idx = fl ? (int64_t)i * St + nbi(-L::cx[i], r) : (int64_t)opp(i) * St + k;
+            else
+                idx = fl ? (int64_t)opp(i) * St + nbi(-L::cx[i], r) : (int64_t)i * St + k;
+            h[i] = decode<PREC>(A[idx], L::w[i], a.h16_scale);
+        }
+        if constexpr (has_tau(OP)) tau_prev = (C)((const T*)a.tau)[k];
+
+        collide_node<LAT, OP, PREC>(h, tau_prev, a.fallback, a.cd, cp, mo, pr, used_fb);
+
+        if constexpr (PAT == PAT_AA_PULL) {
+            // The store of direction opp(i) goes where the load of i came
+            // from; hiding the indices' history from the optimiser keeps it
+            // from holding the 27 load addresses through the collision
+            // (they cost more registers than rebuilding them).  No
+            // instruction is emitted.
+#pragma unroll
+            for (int r = 0; r < 9; ++r) asm volatile("" : "+v"(im[r]), "+v"(wr[r]));
+            asm volatile("" : "+v"(nbf));
+        }
+        S* B = (S*)a.dst;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            int64_t idx;
+            if constexpr (PAT == PAT_AB) {
+                idx = (int64_t)i * St + k;
+            } else {
+                const int r = (1 + L::cy[i]) + 3 * (1 + L::cz[i]);  // row of x + c_i
+                const bool fl = (nbf >> (3 * r + 1 + L::cx[i])) & 1;
+                idx = fl ? (int64_t)i * St + nbi(L::cx[i], r) : (int64_t)opp(i) * St + k;
+            }
+            B[idx] = encode<PREC>(h[i], L::w[i], a.h16_inv);
+        }
+        if constexpr (has_tau(OP)) ((T*)a.tau)[k] = (T)pr.tau_p;
+    }
+    if constexpr (MON)
+        monitor_block<C>(active, mo, pr, cp, used_fb, a.partials + cb * MP_COUNT, a.uprev, k, St);
+}
+
 template <int LAT, int OP, int PREC, int PAT, bool MON>
 static hipError_t go_step(int layout, const StepArgs& a, hipStream_t s)
 {
@@ -454,6 +626,12 @@ static hipError_t go_step(int layout, const StepArgs& a, hipStream_t s)
                 hipLaunchKernelGGL((k_local_slots<LAT, OP, PREC, MON, true>), dim3((unsigned)blocks), dim3(256), 0, s, a);
             else
                 hipLaunchKernelGGL((k_local_slots<LAT, OP, PREC, MON, false>), dim3((unsigned)blocks), dim3(256), 0, s, a);
+        }
+    } else if (layout == LAYOUT_COMPACT && a.pull_slots) {
+        if (a.nfluid > 0) {
+            if constexpr (PAT != PAT_AA_LOCAL)
+                hipLaunchKernelGGL((k_pull_slots<LAT, OP, PREC, PAT, MON>), dim3(8u * (unsigned)a.slot_bpx), dim3(256),
+                                   0, s, a);
         }
     } else if (layout == LAYOUT_COMPACT) {
         hipLaunchKernelGGL((k_step_compact<LAT, OP, PREC, PAT, MON>), grid, dim3(threads), 0, s, a, a.bits, a.wbase);

@@ -22,6 +22,7 @@ OPERATORS = {"PR": 0, "IR": 1, "PRI": 2}
 PRECISIONS = {"FP64": 0, "FP32": 1, "FP16": 2}
 SCHEMES = {"AB": 0, "AA": 1}
 LAYOUTS = {"COMPACT": 0, "DENSE": 1}
+PULL_FORMS = {"AUTO": 0, "SLOTS": 1, "ROWS": 2}
 STATUS = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EHIP", -4: "LBM_ESTATE",
           -5: "LBM_EUNSTABLE", -6: "LBM_EFORMAT"}
 
@@ -69,7 +70,8 @@ EXPORTS = ["lbm_last_error", "lbm_lattice_info", "lbm_query_sizes", "lbm_create"
            "lbm_set_mask", "lbm_init_equilibrium", "lbm_write_populations", "lbm_read_populations",
            "lbm_step", "lbm_time", "lbm_set_monitor_interval", "lbm_read_history", "lbm_monitors",
            "lbm_set_umax_limit", "lbm_read_moments", "lbm_save", "lbm_load", "lbm_set_tile",
-           "lbm_get_tile", "lbm_set_tile_order", "lbm_get_tile_order", "lbm_autotune", "lbm_destroy",
+           "lbm_get_tile", "lbm_set_tile_order", "lbm_get_tile_order", "lbm_set_pull_form", "lbm_get_pull_form",
+           "lbm_autotune", "lbm_destroy",
            "lbm_batch_query_sizes", "lbm_batch_create", "lbm_batch_bind", "lbm_batch_init_equilibrium",
            "lbm_batch_write_populations", "lbm_batch_read_populations", "lbm_batch_read_moments",
            "lbm_batch_set_monitor_interval", "lbm_batch_read_history", "lbm_batch_monitors",
@@ -122,6 +124,8 @@ def load_library(path: str = LIB_PATH):
         "lbm_get_tile": ([vp, i32p, i32p, i32p], ctypes.c_int),
         "lbm_set_tile_order": ([vp, i32, i32], ctypes.c_int),
         "lbm_get_tile_order": ([vp, i32p, i32p], ctypes.c_int),
+        "lbm_set_pull_form": ([vp, i32], ctypes.c_int),
+        "lbm_get_pull_form": ([vp, i32p], ctypes.c_int),
         "lbm_autotune": ([vp, i32], ctypes.c_int),
         "lbm_destroy": ([vp], ctypes.c_int),
         "lbm_batch_query_sizes": ([ctypes.POINTER(lbm_desc), ctypes.POINTER(lbm_rheology), i32,
@@ -295,6 +299,16 @@ def lbm_get_tile_order(h):
     return r.value, p.value
 
 
+def lbm_set_pull_form(h, form):
+    _check(load_library().lbm_set_pull_form(h, PULL_FORMS[form] if isinstance(form, str) else int(form)))
+
+
+def lbm_get_pull_form(h):
+    f = ctypes.c_int32()
+    _check(load_library().lbm_get_pull_form(h, ctypes.byref(f)))
+    return {v: k for k, v in PULL_FORMS.items()}.get(f.value, f.value)
+
+
 def lbm_autotune(h, trial_steps=10):
     _check(load_library().lbm_autotune(h, int(trial_steps)))
 
@@ -425,6 +439,12 @@ class Domain:
 
     def tile_order(self):
         return lbm_get_tile_order(self.h)
+
+    def set_pull_form(self, form):
+        lbm_set_pull_form(self.h, form)
+
+    def pull_form(self):
+        return lbm_get_pull_form(self.h)
 
     def autotune(self, trial_steps=10):
         lbm_autotune(self.h, trial_steps)

@@ -38,7 +38,7 @@ def random_mask(N, seed, fraction):
 
 def run_pair(lat, dims, periodic, op, steps, *, nu_p=0.1, sigma_y=5e-4, m=1e4, g=(2e-5, -1e-5, 5e-6),
              lam=0.25, scheme="AA", precision="FP64", mask=None, seed=1, amp=1e-2, tile=None,
-             gpu_kw=None, flow_axis=0, mrt_bulk=0.0, mrt_even=0.0):
+             gpu_kw=None, flow_axis=0, mrt_bulk=0.0, mrt_even=0.0, pull_form=None):
     """Run the oracle and the library from the same seeded state; return both
     moment sets (and the populations read back)."""
     from paper_1610_01388_amd import lbm
@@ -63,6 +63,9 @@ def run_pair(lat, dims, periodic, op, steps, *, nu_p=0.1, sigma_y=5e-4, m=1e4, g
         dom.set_mask(mask)
     if tile is not None:
         dom.set_tile(*tile)
+    if pull_form is not None:
+        dom.set_pull_form(pull_form)
+        assert dom.pull_form() == pull_form
     dom.write_populations(P0[perm], tau0 if op == "PR" else None)
     dom.step(steps)
     got = dom.moments()

@@ -106,6 +106,12 @@ def test_unbound_domain_refuses_work():
     with pytest.raises(lbm.LbmError):
         lbm.lbm_set_tile(h, 8, 8, 2)  # compact needs one wavefront per 64-node row segment
     lbm.lbm_set_tile(h, 64, 2, 2)
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_set_pull_form(h, 3)
+    assert e.value.code == -1
+    for form in ("SLOTS", "ROWS"):
+        lbm.lbm_set_pull_form(h, form)
+        assert lbm.lbm_get_pull_form(h) == form
     lbm.lbm_destroy(h)
 
 

@@ -31,19 +31,49 @@ def _check_fp64(ref, got, pops, tol_u=1e-10):
         assert np.max(np.abs(tg[fluid] - to[fluid]) / to[fluid]) <= 1e-12
 
 
-@pytest.mark.parametrize("layout", ["COMPACT", "DENSE"])
+@pytest.mark.parametrize("layout,form", [("COMPACT", "ROWS"), ("COMPACT", "SLOTS"), ("DENSE", None)])
 @pytest.mark.parametrize("steps", [30, 31])
 @pytest.mark.parametrize("scheme", ["AA", "AB"])
 @pytest.mark.parametrize("op", ["IR", "PR"])
 @pytest.mark.parametrize("case", range(len(CASES)))
-def test_fp64_parity_random_state(case, op, scheme, steps, layout):
+def test_fp64_parity_random_state(case, op, scheme, steps, layout, form):
     lat, dims, per, frac = CASES[case]
     N = int(np.prod(dims))
     mask = random_mask(N, 100 + case, frac) if frac > 0 else None
-    print(f"parity: lat={lat} dims={dims} op={op} scheme={scheme} steps={steps} layout={layout}", flush=True)
+    print(f"parity: lat={lat} dims={dims} op={op} scheme={scheme} steps={steps} layout={layout} form={form}",
+          flush=True)
     ref, got, pref, pgot = run_pair(lat, dims, per, op, steps, scheme=scheme, mask=mask, seed=7 + case,
-                                    gpu_kw={"layout": layout})
+                                    gpu_kw={"layout": layout}, pull_form=form)
     _check_fp64(ref, got, (pref, pgot))
+
+
+LOW_POROSITY = [(0, (130, 41, 1), (1, 1, 1)), (1, (65, 9, 8), (1, 0, 1)), (2, (1, 13, 11), (1, 1, 0)),
+                (2, (200, 5, 6), (0, 1, 1))]
+
+
+@pytest.mark.parametrize("scheme", ["AA", "AB"])
+@pytest.mark.parametrize("case", range(len(LOW_POROSITY)))
+def test_low_porosity_both_neighbour_kernels(case, scheme):
+    """85% solid (most words nearly empty, many rows without fluid; one
+    case one node wide): the slot kernel, which the default picks below 45%
+    fluid, against the oracle, and bitwise against the row-segment kernel."""
+    from paper_1610_01388_amd import lbm
+    lat, dims, per = LOW_POROSITY[case]
+    N = int(np.prod(dims))
+    mask = random_mask(N, 300 + case, 0.85)
+    out = {}
+    for form in ("SLOTS", "ROWS"):
+        ref, got, pref, pgot = run_pair(lat, dims, per, "IR", 25, scheme=scheme, mask=mask, seed=40 + case,
+                                        pull_form=form)
+        _check_fp64(ref, got, (pref, pgot))
+        out[form] = pgot[0]
+    assert np.array_equal(out["SLOTS"], out["ROWS"])
+    dom = lbm.Domain(("D2Q9", "D3Q19", "D3Q27")[lat], dims, per, "IR", 0.1, 5e-4)
+    dom.set_mask(mask)
+    assert dom.pull_form() == "SLOTS"  # default for this fluid fraction
+    dom.set_mask(np.zeros(N, dtype=np.uint8))
+    assert dom.pull_form() == "ROWS"
+    dom.close()
 
 
 @pytest.mark.parametrize("layout", ["COMPACT", "DENSE"])
@@ -101,3 +131,27 @@ def test_schemes_and_layouts_bitwise(lat, op):
         assert diff == 0.0, f"{key} differs from AA/COMPACT by up to {diff:.3e}"
         for a, b in zip(val[0], ref[0]):
             assert np.array_equal(a, b)
+
+
+def test_neighbour_kernels_bitwise_at_full_size():
+    """The 256^3 D3Q27 sphere pack (porosity 0.7) of the benchmark, FP64,
+    AA: four steps from a seeded random state with the slot kernel and with
+    the row-segment kernel give the same populations bit for bit."""
+    from paper_1610_01388_amd import inputs, lbm
+    from support import perm_lib_from_oracle, random_state
+    n = 256
+    mask, _ = inputs.sphere_pack((n, n, n), 8.0, 0.7, seed=1)
+    case = inputs.porous_case("IR", n=n, Bi=1.0)
+    P0, _ = random_state(2, n ** 3, 29, amp=1e-3)
+    P0 *= (1 - mask)[None, :]
+    P0 = P0[perm_lib_from_oracle(2)]
+    out = {}
+    for form in ("SLOTS", "ROWS"):
+        dom = lbm.Domain("D3Q27", case["dims"], case["periodic"], "IR", case["nu_p"], case["sigma_y"], g=case["g"])
+        dom.set_mask(mask)
+        dom.set_pull_form(form)
+        dom.write_populations(P0)
+        dom.step(4)
+        out[form] = dom.read_populations()[0]
+        dom.close()
+    assert np.array_equal(out["SLOTS"], out["ROWS"])
