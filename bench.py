@@ -62,11 +62,13 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def make_domain(lbm, case, precision, scheme="AA", mask=None, **kw):
+def make_domain(lbm, case, precision, scheme="AA", mask=None, pull_form=None, **kw):
     dom = lbm.Domain(case["lattice"], case["dims"], case["periodic"], case["op"], case["nu_p"],
                      case["sigma_y"], m=case["m"], g=case["g"], precision=precision, scheme=scheme, **kw)
     if mask is not None:
         dom.set_mask(mask)  # also resets the state to rest
+    if pull_form is not None:
+        dom.set_pull_form(pull_form)
     return dom
 
 
@@ -111,6 +113,8 @@ def run_form(torch, lbm, name, case, precision, mask, fluid, warmup, steps, ref=
            "dims": list(case["dims"]), "fluid_nodes": int(fluid), "steps": steps,
            "ms_per_step": ms / steps, "MLUPS": mlups, "algorithmic_GBs": gbs,
            "hbm_frac": gbs / HBM_PEAK_GBS, "bytes_per_node": bpn}
+    if kw.get("layout", "COMPACT") == "COMPACT":
+        out["neighbour_kernel"] = dom.pull_form()
     mom = dom.moments()
     hist = dom.history()
     if hist:
@@ -307,6 +311,7 @@ def main():
     log(f"main: D3Q27 {n}^3 IR FP64 AA {args.layout}, warmup {args.warmup}, steps {args.steps}")
     dom = make_domain(lbm, case, "FP64", mask=mask, layout=args.layout)
     tile = dom.tile()
+    nk = dom.pull_form() if args.layout == "COMPACT" else None
     ms, wall = timed_run(torch, dom, args.warmup, args.steps)
     ref_ir = dom.moments()
     hist = dom.history()
@@ -332,12 +337,13 @@ def main():
                    "layout": args.layout,
                    "dims": [n, n, n], "fluid_nodes": fluid, "porosity": float(1 - mask.mean()),
                    "nu_p": case["nu_p"], "sigma_y": case["sigma_y"], "g": list(case["g"]),
-                   "tile": list(tile), "monitor_every": 100,
+                   "tile": list(tile), "neighbour_kernel": nk, "monitor_every": 100,
                    "parity": "velocity L2-rel <= 1e-10 vs the FP64 oracle (tests/test_gpu_parity.py)"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "algorithmic_bytes_per_launch": per_launch, "bytes_per_fluid_node": bpn,
-                     "kernel": ("k_step_compact<D3Q27, IR, FP64, AA pull> and k_local_slots<D3Q27, IR, FP64> "
+                     "kernel": (("k_step_compact" if nk == "ROWS" else "k_pull_slots")
+                                + "<D3Q27, IR, FP64, AA pull> and k_local_slots<D3Q27, IR, FP64> "
                                 "(AA local)" if args.layout == "COMPACT" else "k_step<D3Q27, IR, FP64, AA pull/local>")
                                + ", mean of the two alternating AA phases",
                      "kernel_source_hash": khash},
@@ -359,6 +365,15 @@ def main():
         pri, _ = run_form(torch, lbm, "PRI FP64 (implicit tau update, no tau field)", case_pri, "FP64", mask, fluid,
                           W, K)
         forms += [f64_ir, f64_pr, dense_ir, pri]
+        log("forms: tight medium (overlapping spheres, porosity 0.15): row-segment vs slot neighbour kernel")
+        mask_t, _ = inputs.overlapping_spheres((n, n, n), 8.0, 0.15, seed=1)
+        fl_t = int((mask_t == 0).sum())
+        tight_rows, ref_t = run_form(torch, lbm, "IR FP64 tight medium, row-segment kernel", case, "FP64", mask_t,
+                                     fl_t, W, K, pull_form="ROWS")
+        tight_auto, _ = run_form(torch, lbm, "IR FP64 tight medium, default kernel choice", case, "FP64", mask_t,
+                                 fl_t, W, K, ref=ref_t)
+        forms += [tight_rows, tight_auto]
+        del ref_t, mask_t
         log("forms: FP32 storage and collision")
         forms.append(run_form(torch, lbm, "IR FP32", case, "FP32", mask, fluid, W, K, ref=ref_ir)[0])
         forms.append(run_form(torch, lbm, "PR FP32", case_pr, "FP32", mask, fluid, W, K, ref=ref_pr)[0])

@@ -125,16 +125,49 @@ def sphere_pack(dims, radius: float = 8.0, porosity: float = 0.7, seed: int = 1,
             continue
         cells.setdefault(tuple(ci), []).append(c)
         centres.append(c)
-        ix = np.arange(int(math.floor(c[0])) - r, int(math.floor(c[0])) + r + 2)
-        iy = np.arange(int(math.floor(c[1])) - r, int(math.floor(c[1])) + r + 2)
-        iz = np.arange(int(math.floor(c[2])) - r, int(math.floor(c[2])) + r + 2)
-        d2 = ((iz[:, None, None] - c[2]) ** 2 + (iy[None, :, None] - c[1]) ** 2
-              + (ix[None, None, :] - c[0]) ** 2)
-        inside = d2 <= radius * radius
-        sub = np.ix_(iz % nz, iy % ny, ix % nx)
-        newly = inside & ~solid[sub]
-        count += int(newly.sum())
-        solid[sub] |= inside
+        count += _stamp_sphere(solid, c, radius)
+    return solid.reshape(-1).astype(np.uint8), np.array(centres)
+
+
+def _stamp_sphere(solid: np.ndarray, c, radius: float) -> int:
+    """Mark the voxels within radius of centre c (periodic, minimum image)
+    solid in the (nz, ny, nx) array; return how many were fluid before."""
+    nz, ny, nx = solid.shape
+    r = int(math.ceil(radius))
+    ix = np.arange(int(math.floor(c[0])) - r, int(math.floor(c[0])) + r + 2)
+    iy = np.arange(int(math.floor(c[1])) - r, int(math.floor(c[1])) + r + 2)
+    iz = np.arange(int(math.floor(c[2])) - r, int(math.floor(c[2])) + r + 2)
+    d2 = ((iz[:, None, None] - c[2]) ** 2 + (iy[None, :, None] - c[1]) ** 2
+          + (ix[None, None, :] - c[0]) ** 2)
+    inside = d2 <= radius * radius
+    sub = np.ix_(iz % nz, iy % ny, ix % nx)
+    newly = int((inside & ~solid[sub]).sum())
+    solid[sub] |= inside
+    return newly
+
+
+def overlapping_spheres(dims, radius: float = 8.0, porosity: float = 0.15, seed: int = 1,
+                        max_spheres: int = 10_000_000):
+    """Tight porous medium: spheres whose centres are uniform in the periodic
+    box (x, y, z order from SplitMix64(seed)) and may overlap (the Boolean
+    model), added until the voxel porosity first drops to <= porosity.  Any
+    porosity is reachable (non-overlapping packings jam near 0.6 solid); the
+    pore space of this model stays connected down to a few percent.
+    Returns (mask, centres[k, 3])."""
+    nx, ny, nz = (int(v) for v in dims)
+    if 2.0 * radius >= min(nx, ny, nz) / 2.0:
+        raise ValueError("box too small for minimum-image voxelisation")
+    N = nx * ny * nz
+    solid = np.zeros((nz, ny, nx), dtype=bool)
+    rng = SplitMix64(seed)
+    centres = []
+    count = 0
+    while 1.0 - count / N > porosity:
+        if len(centres) >= max_spheres:
+            raise RuntimeError("overlapping_spheres: porosity target not reached")
+        c = np.array([rng.uniform() * nx, rng.uniform() * ny, rng.uniform() * nz])
+        centres.append(c)
+        count += _stamp_sphere(solid, c, radius)
     return solid.reshape(-1).astype(np.uint8), np.array(centres)
 
 

@@ -48,6 +48,30 @@ def test_sphere_pack_properties():
     assert np.array_equal(mask, mask2)
 
 
+def test_overlapping_spheres_properties():
+    n, R = 48, 5.0
+    mask, centres = inputs.overlapping_spheres((n, n, n), R, 0.15, seed=3)
+    por = 1.0 - mask.mean()
+    assert por <= 0.15
+    # without the last sphere the porosity was still above the target
+    m3 = np.zeros((n, n, n), dtype=bool)
+    for c in centres[:-1]:
+        inputs._stamp_sphere(m3, c, R)
+    assert 1.0 - m3.mean() > 0.15
+    # Boolean model: porosity exp(-k v / N) for k spheres of voxel volume v
+    v = 4.0 / 3.0 * np.pi * R ** 3
+    assert abs(np.log(por) + len(centres) * v / n ** 3) < 0.05 * len(centres) * v / n ** 3
+    # voxel rule as for the non-overlapping pack (minimum image)
+    mm = mask.reshape(n, n, n)
+    rng = np.random.default_rng(1)
+    for _ in range(300):
+        z, y, x = rng.integers(0, n, 3)
+        dd = centres - np.array([x, y, z])
+        dd -= n * np.round(dd / n)
+        assert mm[z, y, x] == int(((dd ** 2).sum(1) <= R * R).any())
+    assert np.array_equal(mask, inputs.overlapping_spheres((n, n, n), R, 0.15, seed=3)[0])
+
+
 def test_batch_sweep_recipe():
     cases = inputs.batch_sweep()
     assert len(cases) == 256
