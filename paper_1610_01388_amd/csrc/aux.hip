@@ -8,11 +8,6 @@
 
 namespace lbm {
 
-template <int LAT>
-hipError_t launch_step_lattice(int op, int prec, int pat, bool mon, int layout, const StepArgs& a, hipStream_t s);
-template <int LAT>
-hipError_t launch_batch_lattice(int prec, int pat, bool mon, const BatchArgs& a, int grid, hipStream_t s);
-
 // Layout of the stored state (NodeArgs::layout):
 //  0: post-collision, natural slots  (A/B; slot i at x holds P_i(x))
 //  1: post-collision, swapped slots  (AA after an even number of steps;
@@ -480,12 +475,12 @@ hipError_t launch_batch_tick(int64_t* counter, hipStream_t s)
 
 hipError_t launch_step(int lat, int op, int prec, int pat, bool mon, int layout, const StepArgs& a, hipStream_t s)
 {
-    switch (lat) {
-    case 0: return launch_step_lattice<0>(op, prec, pat, mon, layout, a, s);
-    case 1: return launch_step_lattice<1>(op, prec, pat, mon, layout, a, s);
-    case 2: return launch_step_lattice<2>(op, prec, pat, mon, layout, a, s);
-    default: return hipErrorInvalidValue;
-    }
+    if (lat < 0 || lat > 2 || prec < 0 || prec > 2) return hipErrorInvalidValue;
+    static hipError_t (*const table[3][3])(int, int, bool, int, const StepArgs&, hipStream_t) = {
+        {launch_step_prec<0, PREC_F64>, launch_step_prec<0, PREC_F32>, launch_step_prec<0, PREC_F16>},
+        {launch_step_prec<1, PREC_F64>, launch_step_prec<1, PREC_F32>, launch_step_prec<1, PREC_F16>},
+        {launch_step_prec<2, PREC_F64>, launch_step_prec<2, PREC_F32>, launch_step_prec<2, PREC_F16>}};
+    return table[lat][prec](op, pat, mon, layout, a, s);
 }
 
 }  // namespace lbm

@@ -87,7 +87,9 @@ __device__ __forceinline__ void batch_tile(const BatchArgs& a, const BatchSim& s
         C tau_prev = C(0);
         if constexpr (has_tau(OP)) tau_prev = (C)tau[n];
 
-        collide_node<LAT, OP, PREC>(h, tau_prev, a.fallback, sm.cd, cp, mo, pr, used_fb);
+        // the batch keeps the FP64 redo compiled in; its flag decides at run time
+        collide_node<LAT, (PREC != PREC_F64 ? (OP | OP_FB) : OP), PREC>(h, tau_prev, a.fallback, sm.cd, cp, mo, pr,
+                                                                         used_fb);
 
         S* B = (S*)a.pdf + sm.off_pdf;
 #pragma unroll

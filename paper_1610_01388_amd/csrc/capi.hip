@@ -409,7 +409,8 @@ int run_steps(lbm_domain* dm, int64_t nsteps)
             a.dst = dm->pdf;
         }
         const bool mon = dm->mon_k > 0 && (dm->t % dm->mon_k) == 0;
-        HIPCHK(launch_step(dm->d.lattice, kernel_op(dm->r), dm->d.precision, pat, mon, dm->d.layout, a, dm->stream));
+        HIPCHK(launch_step(dm->d.lattice, kernel_op(dm->r) | (a.fallback ? OP_FB : 0), dm->d.precision, pat, mon,
+                           dm->d.layout, a, dm->stream));
         if (mon) {
             char* rec = dm->work + dm->L.hist + (size_t)(dm->hist_written % kHistory) * sizeof(MonitorRecord);
             // the compact slot kernels run one block per 256 fluid slots, the others one per tile

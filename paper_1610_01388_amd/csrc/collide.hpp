@@ -20,8 +20,10 @@ namespace lbm {
 // tau consistent with its own strain rate, found per node; no state).
 // OP_MRT is a flag on PR and PRI: MRT base collision (Sec. 2.1) instead of
 // TRT, a separate kernel instantiation so that the TRT kernels do not carry
-// its registers.
-enum { OP_PR = 0, OP_IR = 1, OP_PRI = 2, OP_MRT = 4 };
+// its registers.  OP_FB, for FP32 / FP16 storage only, compiles in the FP64
+// redo of near-yield nodes (without it the reduced-precision kernels carry
+// no FP64 registers).
+enum { OP_PR = 0, OP_IR = 1, OP_PRI = 2, OP_MRT = 4, OP_FB = 8 };
 __host__ __device__ constexpr int op_base(int op) { return op & 3; }
 // TRT (or MRT) + EDM with a Papanastasiou viscosity
 __host__ __device__ constexpr bool pr_family(int op) { return op_base(op) != OP_IR; }

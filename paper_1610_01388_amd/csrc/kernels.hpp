@@ -138,6 +138,10 @@ struct BatchArgs {
 };
 
 hipError_t launch_step(int lat, int op, int prec, int pat, bool mon, int layout, const StepArgs& a, hipStream_t s);
+template <int LAT, int PREC>
+hipError_t launch_step_prec(int op, int pat, bool mon, int layout, const StepArgs& a, hipStream_t s);
+template <int LAT>
+hipError_t launch_batch_lattice(int prec, int pat, bool mon, const BatchArgs& a, int grid, hipStream_t s);
 hipError_t launch_batch_step(int lat, int prec, int pat, bool mon, const BatchArgs& a, int grid, hipStream_t s);
 hipError_t launch_batch_finalize(const BatchArgs& a, const int* sims_item0, void* records, const int64_t* counter,
                                  int64_t step, int capacity, hipStream_t s);

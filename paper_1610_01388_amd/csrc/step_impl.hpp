@@ -29,7 +29,7 @@ __device__ __forceinline__ void collide_node(typename Store<PREC>::C (&h)[Lattic
     constexpr int Q = Lattice<LAT>::Q;
     mo = moments<LAT>(h);
     pr = rheology<LAT, OP>(mo, cp, tau_prev);
-    if constexpr (PREC != PREC_F64) {
+    if constexpr (PREC != PREC_F64 && (OP & OP_FB) != 0) {
         if (fallback && pr.near_yield) {
             double hd[Q];
 #pragma unroll
@@ -660,38 +660,28 @@ static hipError_t go_pat(int pat, bool mon, int layout, const StepArgs& a, hipSt
     }
 }
 
-template <int LAT>
-hipError_t launch_step_lattice(int op, int prec, int pat, bool mon, int layout, const StepArgs& a, hipStream_t s)
+// One lattice and one storage precision per translation unit.  Reduced
+// precision adds the OP_FB variants (FP64 redo of near-yield nodes).
+template <int LAT, int PREC>
+hipError_t launch_step_prec(int op, int pat, bool mon, int layout, const StepArgs& a, hipStream_t s)
 {
-    if (op == OP_PR) {
-        switch (prec) {
-        case PREC_F64: return go_pat<LAT, OP_PR, PREC_F64>(pat, mon, layout, a, s);
-        case PREC_F32: return go_pat<LAT, OP_PR, PREC_F32>(pat, mon, layout, a, s);
-        case PREC_F16: return go_pat<LAT, OP_PR, PREC_F16>(pat, mon, layout, a, s);
-        }
-    } else if (op == OP_PRI) {
-        switch (prec) {
-        case PREC_F64: return go_pat<LAT, OP_PRI, PREC_F64>(pat, mon, layout, a, s);
-        case PREC_F32: return go_pat<LAT, OP_PRI, PREC_F32>(pat, mon, layout, a, s);
-        case PREC_F16: return go_pat<LAT, OP_PRI, PREC_F16>(pat, mon, layout, a, s);
-        }
-    } else if (op == (OP_PR | OP_MRT)) {
-        switch (prec) {
-        case PREC_F64: return go_pat<LAT, OP_PR | OP_MRT, PREC_F64>(pat, mon, layout, a, s);
-        case PREC_F32: return go_pat<LAT, OP_PR | OP_MRT, PREC_F32>(pat, mon, layout, a, s);
-        case PREC_F16: return go_pat<LAT, OP_PR | OP_MRT, PREC_F16>(pat, mon, layout, a, s);
-        }
-    } else if (op == (OP_PRI | OP_MRT)) {
-        switch (prec) {
-        case PREC_F64: return go_pat<LAT, OP_PRI | OP_MRT, PREC_F64>(pat, mon, layout, a, s);
-        case PREC_F32: return go_pat<LAT, OP_PRI | OP_MRT, PREC_F32>(pat, mon, layout, a, s);
-        case PREC_F16: return go_pat<LAT, OP_PRI | OP_MRT, PREC_F16>(pat, mon, layout, a, s);
-        }
-    } else if (op == OP_IR) {
-        switch (prec) {
-        case PREC_F64: return go_pat<LAT, OP_IR, PREC_F64>(pat, mon, layout, a, s);
-        case PREC_F32: return go_pat<LAT, OP_IR, PREC_F32>(pat, mon, layout, a, s);
-        case PREC_F16: return go_pat<LAT, OP_IR, PREC_F16>(pat, mon, layout, a, s);
+    constexpr int FB = PREC != PREC_F64 ? OP_FB : 0;
+    switch (op) {
+    case OP_PR: return go_pat<LAT, OP_PR, PREC>(pat, mon, layout, a, s);
+    case OP_PRI: return go_pat<LAT, OP_PRI, PREC>(pat, mon, layout, a, s);
+    case OP_PR | OP_MRT: return go_pat<LAT, OP_PR | OP_MRT, PREC>(pat, mon, layout, a, s);
+    case OP_PRI | OP_MRT: return go_pat<LAT, OP_PRI | OP_MRT, PREC>(pat, mon, layout, a, s);
+    case OP_IR: return go_pat<LAT, OP_IR, PREC>(pat, mon, layout, a, s);
+    default: break;
+    }
+    if constexpr (FB != 0) {
+        switch (op) {
+        case OP_PR | FB: return go_pat<LAT, OP_PR | FB, PREC>(pat, mon, layout, a, s);
+        case OP_PRI | FB: return go_pat<LAT, OP_PRI | FB, PREC>(pat, mon, layout, a, s);
+        case OP_PR | OP_MRT | FB: return go_pat<LAT, OP_PR | OP_MRT | FB, PREC>(pat, mon, layout, a, s);
+        case OP_PRI | OP_MRT | FB: return go_pat<LAT, OP_PRI | OP_MRT | FB, PREC>(pat, mon, layout, a, s);
+        case OP_IR | FB: return go_pat<LAT, OP_IR | FB, PREC>(pat, mon, layout, a, s);
+        default: break;
         }
     }
     return hipErrorInvalidValue;
