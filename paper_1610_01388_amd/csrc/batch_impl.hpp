@@ -87,9 +87,7 @@ __device__ __forceinline__ void batch_tile(const BatchArgs& a, const BatchSim& s
         C tau_prev = C(0);
         if constexpr (has_tau(OP)) tau_prev = (C)tau[n];
 
-        // the batch keeps the FP64 redo compiled in; its flag decides at run time
-        collide_node<LAT, (PREC != PREC_F64 ? (OP | OP_FB) : OP), PREC>(h, tau_prev, a.fallback, sm.cd, cp, mo, pr,
-                                                                         used_fb);
+        collide_node<LAT, OP, PREC>(h, tau_prev, a.fallback, sm.cd, cp, mo, pr, used_fb);
 
         S* B = (S*)a.pdf + sm.off_pdf;
 #pragma unroll
@@ -117,9 +115,12 @@ __device__ __forceinline__ void batch_tile(const BatchArgs& a, const BatchSim& s
 // into 8 contiguous chunks and the blocks b with b mod 8 == j, which the
 // hardware places on one XCD, walk chunk j; neighbouring tiles of a
 // simulation then share that XCD's L2.  Both orders visit every item once.
-template <int LAT, int PREC, int PAT, bool MON>
+// FB: the FP64 redo of near-yield nodes compiled in (reduced precision with
+// the fallback on); without it the kernel holds no FP64 registers.
+template <int LAT, int PREC, int PAT, bool MON, bool FB>
 __global__ __launch_bounds__(256) void k_batch_step(const BatchArgs a)
 {
+    constexpr int F = FB ? OP_FB : 0;
     int hi = a.nitems, first = blockIdx.x, stride = gridDim.x;
     if (a.xcd_chunks) {
         const int chunk = (a.nitems + 7) >> 3;
@@ -133,8 +134,8 @@ __global__ __launch_bounds__(256) void k_batch_step(const BatchArgs a)
         const BatchSim& sm = a.sims[sim];
         // PR or IR (the host rejects PRI for batches: its Newton solve would
         // raise the register count of this shared kernel for every item)
-        if (sm.op == OP_PR) batch_tile<LAT, OP_PR, PREC, PAT, MON>(a, sm, item);
-        else batch_tile<LAT, OP_IR, PREC, PAT, MON>(a, sm, item);
+        if (sm.op == OP_PR) batch_tile<LAT, OP_PR | F, PREC, PAT, MON>(a, sm, item);
+        else batch_tile<LAT, OP_IR | F, PREC, PAT, MON>(a, sm, item);
         // the block reduction's LDS slots are read by thread 0 after its
         // barrier; the next item must not overwrite them before that
         if constexpr (MON) __syncthreads();
@@ -145,8 +146,13 @@ template <int LAT>
 hipError_t launch_batch_lattice(int prec, int pat, bool mon, const BatchArgs& a, int grid, hipStream_t s)
 {
     auto go = [&](auto P, auto PT, auto M) {
-        hipLaunchKernelGGL((k_batch_step<LAT, decltype(P)::value, decltype(PT)::value, decltype(M)::value>),
-                           dim3(grid), dim3(256), 0, s, a);
+        constexpr int PV = decltype(P)::value;
+        if (PV != PREC_F64 && a.fallback)
+            hipLaunchKernelGGL((k_batch_step<LAT, PV, decltype(PT)::value, decltype(M)::value, PV != PREC_F64>),
+                               dim3(grid), dim3(256), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_batch_step<LAT, PV, decltype(PT)::value, decltype(M)::value, false>), dim3(grid),
+                               dim3(256), 0, s, a);
         return hipGetLastError();
     };
     using std::integral_constant;
