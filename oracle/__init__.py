@@ -22,7 +22,7 @@ LIB = os.path.join(HERE, "liboracle.so")
 _LIB_OVERRIDE = os.environ.get("LBM_ORACLE_LIB")
 
 D2Q9, D3Q19, D3Q27 = 0, 1, 2
-PR, IR, BGK, PRI = 0, 1, 2, 3
+PR, IR, BGK, PRI, IRHB = 0, 1, 2, 3, 4
 
 
 def build(force: bool = True) -> str:
@@ -40,15 +40,17 @@ class Rheology(ctypes.Structure):
                 ("nu_p", ctypes.c_double), ("sigma_y", ctypes.c_double),
                 ("m", ctypes.c_double), ("gamma_c", ctypes.c_double),
                 ("lambda_", ctypes.c_double), ("g", ctypes.c_double * 3),
-                ("mrt_bulk", ctypes.c_double), ("mrt_even", ctypes.c_double)]
+                ("mrt_bulk", ctypes.c_double), ("mrt_even", ctypes.c_double), ("hb_n", ctypes.c_double)]
 
 
 def rheology(op, nu_p, sigma_y=0.0, m=0.0, gamma_c=1e-8, lam=0.25, g=(0.0, 0.0, 0.0), flow_axis=0,
-             mrt_bulk=0.0, mrt_even=0.0):
+             mrt_bulk=0.0, mrt_even=0.0, hb_n=1.0):
     """flow_axis: 0 off, 1/2/3 = x/y/z -- drop the axis-normal component
     from the collision (Sec. 4.2.2).  mrt_bulk, mrt_even: MRT rates of the
-    bulk moment and of the even moments of order >= 4 (0: TRT)."""
+    bulk moment and of the even moments of order >= 4 (0: TRT).  IRHB:
+    nu_p is the consistency K and hb_n the flow index."""
     r = Rheology()
+    r.hb_n = hb_n
     r.op = op
     r.flow_axis = flow_axis
     r.mrt_bulk = mrt_bulk

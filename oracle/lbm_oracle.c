@@ -329,6 +329,34 @@ static void collide_pr(const lattice_t* L, const orc_rheology* rh, const double*
  * IR: implicitly-regularised model (Sec. 2.3 and 3.2) with its own body
  * force term (Sec. 2.4, Eq. 35).
  * ------------------------------------------------------------------------- */
+/* Herschel-Bulkley law written in s, in the manner of Eq. 38.  With a
+ * Newtonian law Eqs. 32-33 identify D = 3 s / 2 (per unit density), so the
+ * strain rate is g = sqrt(2 D:D) = 3 |s| / sqrt(2).  The law
+ * sigma = 2 nu_app(g) D with nu_app = K g^(n-1) + sigma_y / g then reads
+ * sigma = (3 K (3|s|/sqrt 2)^(n-1) + sqrt(2) sigma_y / |s|) s, which is
+ * Eq. 38 for n = 1, K = nu_p.  With s and sigma along -T (as in the
+ * Bingham case) the contraction of Eq. 31 leaves one equation for |s|:
+ * F(s) = s/2 + 3 K (3/sqrt 2)^(n-1) s^n + sqrt(2) sigma_y - |T| = 0.
+ * F increases with s, is negative at s = 0 when |T| > sqrt(2) sigma_y and
+ * positive at s = 2 (|T| - sqrt(2) sigma_y): bisection to adjacent doubles. */
+static double hb_F(const orc_rheology* rh, double s, double Tn)
+{
+    const double c = 3.0 * rh->nu_p * pow(3.0 / sqrt(2.0), rh->hb_n - 1.0);
+    return 0.5 * s + c * pow(s, rh->hb_n) + sqrt(2.0) * rh->sigma_y - Tn;
+}
+
+static double hb_root(const orc_rheology* rh, double Tn)
+{
+    double lo = 0.0, hi = 2.0 * (Tn - sqrt(2.0) * rh->sigma_y);
+    for (int it = 0; it < 4000; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        if (hb_F(rh, mid, Tn) > 0.0) hi = mid;
+        else lo = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
 static void collide_ir(const lattice_t* L, const orc_rheology* rh, const double* fbar,
                        double* fpost, double* out)
 {
@@ -378,11 +406,18 @@ static void collide_ir(const lattice_t* L, const orc_rheology* rh, const double*
     /* Solve s/2 + T = -sigma (Eq. 31) with the Bingham law written in s
      * (Eq. 38): closed forms of Eqs. 39-40.  Reading: the yield test printed
      * as T >= sigma_y is T > sqrt(2) sigma_y -- the value at which the
-     * yielded branch gives s = 0, so both branches meet there. */
+     * yielded branch gives s = 0, so both branches meet there.  IRHB: the
+     * same equation for a Herschel-Bulkley fluid, solved numerically. */
     int unyielded;
     if (Tn > sqrt2 * rh->sigma_y) {
-        double s_mag = (Tn - sqrt2 * rh->sigma_y) / (0.5 + 3.0 * rh->nu_p);
-        double sig_mag = (6.0 * rh->nu_p * Tn + sqrt2 * rh->sigma_y) / (1.0 + 6.0 * rh->nu_p);
+        double s_mag, sig_mag;
+        if (rh->op == ORC_IRHB) {
+            s_mag = hb_root(rh, Tn);
+            sig_mag = Tn - 0.5 * s_mag;  /* contraction of Eq. 31 with s, sigma along -T */
+        } else {
+            s_mag = (Tn - sqrt2 * rh->sigma_y) / (0.5 + 3.0 * rh->nu_p);
+            sig_mag = (6.0 * rh->nu_p * Tn + sqrt2 * rh->sigma_y) / (1.0 + 6.0 * rh->nu_p);
+        }
         for (int a = 0; a < 3; ++a)
             for (int b = 0; b < 3; ++b) {
                 s[a][b] = -s_mag * Tdev[a][b] / Tn;
@@ -655,7 +690,7 @@ static void collide_node(const orc_domain* dom, const double* fbar, double tau_p
         *nu_app = out[1];
         for (int a = 0; a < 3; ++a) u_out[a] = out[3 + a];
         *unyielded = (int)out[6];
-    } else if (dom->rh.op == ORC_IR) {
+    } else if (dom->rh.op == ORC_IR || dom->rh.op == ORC_IRHB) {
         collide_ir(&dom->L, &dom->rh, fbar, fpost, out);
         *tau_new = tau_prev;
         *nu_app = 0.0;

@@ -27,13 +27,15 @@ extern "C" {
 #endif
 
 enum { ORC_D2Q9 = 0, ORC_D3Q19 = 1, ORC_D3Q27 = 2 };
-enum { ORC_PR = 0, ORC_IR = 1, ORC_BGK = 2, ORC_PRI = 3 };
+enum { ORC_PR = 0, ORC_IR = 1, ORC_BGK = 2, ORC_PRI = 3, ORC_IRHB = 4 };
 
 /* Rheology and forcing.  op: ORC_PR (Papanastasiou-regularised, TRT + EDM,
  * explicit relaxation-time update), ORC_IR (implicitly-regularised),
  * ORC_BGK (Newtonian BGK + EDM reference, tau = 1/2 + 3 nu_p), ORC_PRI (PR
  * with the implicit relaxation-time update of Sec. 3: no state carried
- * between steps). */
+ * between steps), ORC_IRHB (the implicit construction of Sec. 2.3 solved
+ * for a Herschel-Bulkley fluid, as Sec. 3.2 notes it can be: nu_p is the
+ * consistency K, hb_n the flow index; hb_n = 1 is the Bingham IR). */
 typedef struct {
     int32_t op;
     int32_t flow_axis; /* 0: off; 1, 2, 3: the flow is known to be along x, y,
@@ -50,6 +52,7 @@ typedef struct {
     double mrt_even;  /* the bulk (trace) moment and of the even moments of  */
                       /* order >= 4; 0 = the shear rate (TRT).  Odd moments   */
                       /* keep the magic-number rate.  Both 0: plain TRT.      */
+    double hb_n;      /* IRHB: flow index n > 0 of sigma = sigma_y + K g^n   */
 } orc_rheology;
 
 typedef struct orc_domain orc_domain;
@@ -74,7 +77,8 @@ int orc_collide_ir(int lattice, const orc_rheology* rh, const double* fbar,
                    double* fpost, double* out);
 int orc_collide_bgk(int lattice, const orc_rheology* rh, const double* fbar,
                     double* fpost, double* out);
-/* PRI: out as PR (out[0] = the self-consistent relaxation time). */
+/* PRI: out as PR (out[0] = the self-consistent relaxation time).
+ * IRHB: use orc_collide_ir with rh->op == ORC_IRHB (out as IR). */
 int orc_collide_pri(int lattice, const orc_rheology* rh, const double* fbar,
                     double* fpost, double* out);
 

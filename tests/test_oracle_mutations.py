@@ -49,18 +49,22 @@ MUTATIONS = {
                                     "for (int i = 0; i < L->q; ++i) out[i] += sk * L->mrt[k][i] / L->q;"),
     "flow_axis_pr_ignored": ("can be set to zero. */\n    if (rh->flow_axis >= 1 && rh->flow_axis <= 3) D[rh->flow_axis - 1]",
                              "can be set to zero. */\n    if (0) D[rh->flow_axis - 1]"),
+    "hb_strain_factor_exponent": ("pow(3.0 / sqrt(2.0), rh->hb_n - 1.0)", "pow(3.0 / sqrt(2.0), rh->hb_n)"),
+    "hb_stress_from_full_s": ("sig_mag = Tn - 0.5 * s_mag;", "sig_mag = Tn - s_mag;"),
+    "hb_bracket_too_small": ("double lo = 0.0, hi = 2.0 * (Tn - sqrt(2.0) * rh->sigma_y);",
+                             "double lo = 0.0, hi = (Tn - sqrt(2.0) * rh->sigma_y);"),
     "flow_axis_pri_ignored": ("(2.0 * rho * CS2);\n    if (rh->flow_axis >= 1 && rh->flow_axis <= 3) D[rh->flow_axis - 1]",
                               "(2.0 * rho * CS2);\n    if (0) D[rh->flow_axis - 1]"),
 }
 
 PIN_TESTS = ["tests/test_oracle_lattice.py", "tests/test_oracle_operators.py",
              "tests/test_oracle_flows.py", "tests/test_oracle_residual.py", "tests/test_oracle_burnett.py",
-             "tests/test_oracle_mrt.py", "tests/test_oracle_pri.py"]
+             "tests/test_oracle_mrt.py", "tests/test_oracle_pri.py", "tests/test_oracle_hb.py"]
 # The pin file aimed at a mutation's area runs first (all files still run
 # until one fails), so that the suite does not spend minutes on flow pins
 # before reaching the one that targets the mistake.
 FIRST = {"residual_": "tests/test_oracle_residual.py", "flow_axis_": "tests/test_oracle_burnett.py",
-         "pri_": "tests/test_oracle_pri.py", "mrt_": "tests/test_oracle_mrt.py"}
+         "pri_": "tests/test_oracle_pri.py", "mrt_": "tests/test_oracle_mrt.py", "hb_": "tests/test_oracle_hb.py"}
 
 
 def _pin_order(name):
