@@ -62,8 +62,15 @@ typedef enum { LBM_D2Q9 = 0, LBM_D3Q19 = 1, LBM_D3Q27 = 2 } lbm_lattice;
  * 2.3, 3.2).  LBM_PRI: the PR model with the implicit update of Sec. 3: the
  * tau consistent with its own strain rate, found per node each step by
  * bracketed Newton iterations; nothing is kept between steps (no tau
- * buffer). */
-typedef enum { LBM_PR = 0, LBM_IR = 1, LBM_PRI = 2 } lbm_operator;
+ * buffer).  LBM_IRHB: the implicit construction of LBM_IR (Sec. 2.3, Eq.
+ * 31) solved for a Herschel-Bulkley fluid, sigma = sigma_y + K g^n, as Sec.
+ * 3.2 notes other laws can be: nu_p is the consistency K, hb_n the flow
+ * index n (n = 1: Bingham; sigma_y = 0: power-law fluid).  With the strain
+ * rate g = 3|s|/sqrt(2) the contraction of Eq. 31 gives
+ * s/2 + 3 K (3/sqrt 2)^(n-1) s^n + sqrt(2) sigma_y = |dev T| for the
+ * magnitude s of the collision's second moment, solved per node by
+ * bracketed Newton iterations. */
+typedef enum { LBM_PR = 0, LBM_IR = 1, LBM_PRI = 2, LBM_IRHB = 3 } lbm_operator;
 /* Storage of the populations.  All three store deviations h_i = f_i - w_i
  * rho0.  FP64: h in double, collision in double.  FP32: h in float,
  * collision in float.  FP16: h_i * 2^k / w_i in IEEE half (k =
@@ -125,6 +132,8 @@ typedef struct {
                                 magic-number rate, the rest).  IR: must be 0;
                                 PRI: mrt_bulk must be 0.  Out of [0, 2):
                                 EINVAL. */
+    double hb_n;             /* IRHB: flow index n in [0.2, 5]; other
+                                operators: ignored */
 } lbm_rheology;
 
 typedef struct {
@@ -170,7 +179,8 @@ int lbm_query_sizes(const lbm_desc* desc, const lbm_rheology* rh, lbm_sizes* out
 /* Validate and create a domain.  Errors (LBM_EINVAL): unknown lattice,
  * precision or scheme; non-positive sizes; nz != 1 for D2Q9; nu_p <= 0;
  * sigma_y < 0; rho0 <= 0; PR with m < 0, gamma_c <= 0 or lambda_trt <= 0;
- * fp16_scale_log2 outside 0..24; fallback_band < 0. */
+ * fp16_scale_log2 outside 0..24; fallback_band < 0; IRHB with hb_n outside
+ * [0.2, 5]. */
 int lbm_create(const lbm_desc* desc, const lbm_rheology* rh, lbm_domain** out);
 
 /* Bind caller-owned device buffers (sizes from lbm_query_sizes; tau may be

@@ -391,7 +391,7 @@ hipError_t launch_readout(int lat, int op, int prec, const NodeArgs& a, hipStrea
         else if (op == (OP_PRI | OP_MRT))
             hipLaunchKernelGGL((k_readout<decltype(L)::value, OP_PRI | OP_MRT, decltype(P)::value>),
                                dim3(nblk(a.count)), dim3(256), 0, s, a);
-        else
+        else  // IR and IRHB: the readout (velocity, yield flag) does not depend on the law's solve
             hipLaunchKernelGGL((k_readout<decltype(L)::value, OP_IR, decltype(P)::value>), dim3(nblk(a.count)),
                                dim3(256), 0, s, a);
         return hipGetLastError();

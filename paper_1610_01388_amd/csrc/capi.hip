@@ -59,7 +59,8 @@ static_assert((int)LAYOUT_COMPACT == (int)LBM_COMPACT && (int)LAYOUT_DENSE == (i
               "kernel layout codes must equal the C ABI's lbm_layout values");
 static_assert((int)PREC_F64 == (int)LBM_FP64 && (int)PREC_F32 == (int)LBM_FP32 && (int)PREC_F16 == (int)LBM_FP16,
               "kernel precision codes must equal the C ABI's lbm_precision values");
-static_assert((int)OP_PR == (int)LBM_PR && (int)OP_IR == (int)LBM_IR && (int)OP_PRI == (int)LBM_PRI,
+static_assert((int)OP_PR == (int)LBM_PR && (int)OP_IR == (int)LBM_IR && (int)OP_PRI == (int)LBM_PRI &&
+                  (int)OP_IRHB == (int)LBM_IRHB,
               "kernel operator codes must equal the C ABI's lbm_operator values");
 
 int lattice_q(int lat) { return lat == 0 ? 9 : lat == 1 ? 19 : lat == 2 ? 27 : -1; }
@@ -108,7 +109,10 @@ int check_desc(const lbm_desc* d)
 int check_rheology(const lbm_rheology* r)
 {
     if (!r) return fail(LBM_EINVAL, "rheology is NULL");
-    if (r->op != LBM_PR && r->op != LBM_IR && r->op != LBM_PRI) return fail(LBM_EINVAL, "unknown operator %d", r->op);
+    if (r->op != LBM_PR && r->op != LBM_IR && r->op != LBM_PRI && r->op != LBM_IRHB)
+        return fail(LBM_EINVAL, "unknown operator %d", r->op);
+    if (r->op == LBM_IRHB && !(r->hb_n >= 0.2 && r->hb_n <= 5.0))
+        return fail(LBM_EINVAL, "hb_n (flow index) must lie in [0.2, 5]");
     if (!(r->nu_p > 0)) return fail(LBM_EINVAL, "nu_p must be > 0 (tau > 1/2)");
     if (!(r->sigma_y >= 0)) return fail(LBM_EINVAL, "sigma_y must be >= 0");
     if (!(r->rho0 > 0)) return fail(LBM_EINVAL, "rho0 must be > 0");
@@ -124,7 +128,7 @@ int check_rheology(const lbm_rheology* r)
     if (r->flow_axis < 0 || r->flow_axis > 3) return fail(LBM_EINVAL, "flow_axis must be 0 (off) or 1..3");
     if (!(r->mrt_bulk >= 0 && r->mrt_bulk < 2) || !(r->mrt_even >= 0 && r->mrt_even < 2))
         return fail(LBM_EINVAL, "MRT rates must lie in [0, 2) (0: the shear rate)");
-    if ((r->mrt_bulk > 0 || r->mrt_even > 0) && r->op == LBM_IR)
+    if ((r->mrt_bulk > 0 || r->mrt_even > 0) && (r->op == LBM_IR || r->op == LBM_IRHB))
         return fail(LBM_EINVAL, "the MRT base collision applies to the PR operators");
     if (r->mrt_bulk > 0 && r->op == LBM_PRI)
         return fail(LBM_EINVAL, "PRI takes no separate MRT bulk rate (its tau solve scales the whole strain rate)");
@@ -265,6 +269,8 @@ Coll<C> make_coll(const lbm_rheology& r)
     c.axis = r.flow_axis;
     c.mrt_b = (C)r.mrt_bulk;
     c.mrt_e = (C)r.mrt_even;
+    c.hb_n = (C)r.hb_n;
+    c.hb_c = (C)(3.0 * r.nu_p * std::pow(3.0 / std::sqrt(2.0), r.hb_n - 1.0));
     return c;
 }
 

@@ -17,16 +17,18 @@ namespace lbm {
 // PR: Papanastasiou-regularised with the explicit relaxation-time update
 // (the strain rate uses the previous step's tau, kept per node); IR:
 // implicitly regularised; PRI: PR with the implicit update of Sec. 3 (the
-// tau consistent with its own strain rate, found per node; no state).
+// tau consistent with its own strain rate, found per node; no state);
+// IRHB: the IR construction for a Herschel-Bulkley fluid (K = nu_p, flow
+// index n), its collision moment found per node (Sec. 3.2).
 // OP_MRT is a flag on PR and PRI: MRT base collision (Sec. 2.1) instead of
 // TRT, a separate kernel instantiation so that the TRT kernels do not carry
 // its registers.  OP_FB, for FP32 / FP16 storage only, compiles in the FP64
 // redo of near-yield nodes (without it the reduced-precision kernels carry
 // no FP64 registers).
-enum { OP_PR = 0, OP_IR = 1, OP_PRI = 2, OP_MRT = 4, OP_FB = 8 };
+enum { OP_PR = 0, OP_IR = 1, OP_PRI = 2, OP_IRHB = 3, OP_MRT = 4, OP_FB = 8 };
 __host__ __device__ constexpr int op_base(int op) { return op & 3; }
 // TRT (or MRT) + EDM with a Papanastasiou viscosity
-__host__ __device__ constexpr bool pr_family(int op) { return op_base(op) != OP_IR; }
+__host__ __device__ constexpr bool pr_family(int op) { return op_base(op) == OP_PR || op_base(op) == OP_PRI; }
 // carries a relaxation-time field from step to step
 __host__ __device__ constexpr bool has_tau(int op) { return op_base(op) == OP_PR; }
 __host__ __device__ constexpr bool is_mrt(int op) { return (op & OP_MRT) != 0; }
@@ -46,6 +48,7 @@ template <class C> struct Coll {
     C band;       // FP64 fallback band
     int axis;     // 0, or 1..3: known flow axis whose normal component the collision drops (Sec. 4.2.2)
     C mrt_b, mrt_e;  // MRT rates of the bulk moment and of the even moments of order >= 4 (<= 0: shear rate)
+    C hb_n, hb_c;    // IRHB: flow index n and 3 K (3/sqrt 2)^(n-1)
 };
 
 template <class C> struct Moments {
@@ -167,6 +170,44 @@ __device__ __forceinline__ C implicit_tau(C G, const Coll<C>& p, C irho)
     return x;
 }
 
+__device__ __forceinline__ double d_pow(double b, double e) { return pow(b, e); }
+__device__ __forceinline__ float d_pow(float b, float e) { return powf(b, e); }
+
+// IRHB: magnitude s of the collision's second moment for a yielded node
+// (Tn > sqrt(2) sigma_y).  The Herschel-Bulkley law written in s with the
+// strain rate 3 s / sqrt(2) turns the contraction of Eq. 31 into
+// F(s) = s/2 + c s^n + sqrt(2) sigma_y - Tn = 0, c = 3 K (3/sqrt 2)^(n-1):
+// increasing in s and negative at 0; with e = Tn - sqrt(2) sigma_y the root
+// lies below both 2 e (from s/2 <= e) and (e / c)^(1/n) (from c s^n <= e),
+// the second bound close to it when the power term dominates (small n).
+// Newton's method kept inside the shrinking bracket (bisection whenever a
+// step would leave it) from the n = 1 closed form (exact for Bingham), until
+// a step falls below the precision's resolution.  A bound that underflows
+// to zero returns zero (s is then negligible against Tn).
+template <class C>
+__device__ __forceinline__ C hb_moment(C Tn, const Coll<C>& p)
+{
+    const C e = Tn - p.sqrt2_sy;
+    C lo = C(0), hi = fmin(C(2) * e, d_pow(e / p.hb_c, C(1) / p.hb_n));
+    if (!(hi > C(0))) return C(0);
+    C x = fmin(e / (C(0.5) + p.hb_c), hi);
+    const C tol = sizeof(C) == 8 ? C(1e-14) : C(2e-7);
+    for (int it = 0; it < 64; ++it) {
+        const C xn1 = d_pow(x, p.hb_n - C(1));  // s^(n-1); x > 0 here
+        const C F = C(0.5) * x + p.hb_c * xn1 * x - e;
+        if (F > C(0)) hi = x;
+        else lo = x;
+        const C step = F / (C(0.5) + p.hb_c * p.hb_n * xn1);
+        C xn = x - step;
+        const bool conv = fabs(step) <= tol * x;
+        if (!conv && !(xn > lo && xn < hi)) xn = C(0.5) * (lo + hi);
+        const bool done = conv || hi - lo <= tol * hi;
+        x = xn;
+        if (done) break;
+    }
+    return x;
+}
+
 // Rheology: everything up to, but not including, the relaxation.
 //  PR (Sec. 2.2 Eq. 24, Sec. 3.1 Eqs. 36-37, Sec. 2.1): D from the
 //   non-equilibrium second moment at the bare velocity with the previous
@@ -253,7 +294,10 @@ __device__ __forceinline__ Pre<C> rheology(const Moments<C>& mo, const Coll<C>& 
         const C Tn = d_sqrt(frob2(t));
         const bool yielded = Tn > p.sqrt2_sy;
         C lam = C(1);
-        if (yielded) lam = p.ir_a + p.ir_b / Tn;
+        if (yielded) {
+            if constexpr (op_base(OP) == OP_IRHB) lam = C(1) - hb_moment(Tn, p) / Tn;
+            else lam = p.ir_a + p.ir_b / Tn;
+        }
 #pragma unroll
         for (int a = 0; a < 6; ++a) r.a[a] = lam * t[a];
         r.Tn = Tn;

@@ -672,6 +672,7 @@ hipError_t launch_step_prec(int op, int pat, bool mon, int layout, const StepArg
     case OP_PR | OP_MRT: return go_pat<LAT, OP_PR | OP_MRT, PREC>(pat, mon, layout, a, s);
     case OP_PRI | OP_MRT: return go_pat<LAT, OP_PRI | OP_MRT, PREC>(pat, mon, layout, a, s);
     case OP_IR: return go_pat<LAT, OP_IR, PREC>(pat, mon, layout, a, s);
+    case OP_IRHB: return go_pat<LAT, OP_IRHB, PREC>(pat, mon, layout, a, s);
     default: break;
     }
     if constexpr (FB != 0) {
@@ -681,6 +682,7 @@ hipError_t launch_step_prec(int op, int pat, bool mon, int layout, const StepArg
         case OP_PR | OP_MRT | FB: return go_pat<LAT, OP_PR | OP_MRT | FB, PREC>(pat, mon, layout, a, s);
         case OP_PRI | OP_MRT | FB: return go_pat<LAT, OP_PRI | OP_MRT | FB, PREC>(pat, mon, layout, a, s);
         case OP_IR | FB: return go_pat<LAT, OP_IR | FB, PREC>(pat, mon, layout, a, s);
+        case OP_IRHB | FB: return go_pat<LAT, OP_IRHB | FB, PREC>(pat, mon, layout, a, s);
         default: break;
         }
     }

@@ -18,7 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblbm.so")
 
 LATTICES = {"D2Q9": 0, "D3Q19": 1, "D3Q27": 2}
-OPERATORS = {"PR": 0, "IR": 1, "PRI": 2}
+OPERATORS = {"PR": 0, "IR": 1, "PRI": 2, "IRHB": 3}
 PRECISIONS = {"FP64": 0, "FP32": 1, "FP16": 2}
 SCHEMES = {"AB": 0, "AA": 1}
 LAYOUTS = {"COMPACT": 0, "DENSE": 1}
@@ -45,7 +45,7 @@ class lbm_rheology(ctypes.Structure):
                 ("m", ctypes.c_double), ("gamma_c", ctypes.c_double), ("lambda_trt", ctypes.c_double),
                 ("g", ctypes.c_double * 3), ("fallback_band", ctypes.c_double),
                 ("fp16_scale_log2", ctypes.c_int32), ("flow_axis", ctypes.c_int32),
-                ("mrt_bulk", ctypes.c_double), ("mrt_even", ctypes.c_double)]
+                ("mrt_bulk", ctypes.c_double), ("mrt_even", ctypes.c_double), ("hb_n", ctypes.c_double)]
 
 
 class lbm_monitor(ctypes.Structure):
@@ -333,8 +333,9 @@ def make_desc(lattice, dims, periodic, precision="FP64", scheme="AA", layout="CO
 
 def make_rheology(op, nu_p, sigma_y=0.0, m=0.0, g=(0.0, 0.0, 0.0), rho0=1.0, gamma_c=1e-8,
                   lambda_trt=0.25, fp64_fallback=False, fallback_band=0.0, fp16_scale_log2=14, flow_axis=0,
-                  mrt_bulk=0.0, mrt_even=0.0):
+                  mrt_bulk=0.0, mrt_even=0.0, hb_n=1.0):
     r = lbm_rheology()
+    r.hb_n = float(hb_n)
     r.op = OPERATORS[op] if isinstance(op, str) else int(op)
     r.fp64_fallback = int(bool(fp64_fallback))
     r.nu_p, r.sigma_y, r.rho0 = float(nu_p), float(sigma_y), float(rho0)

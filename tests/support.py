@@ -7,7 +7,7 @@ import oracle
 from paper_1610_01388_amd import inputs
 
 LAT_NAMES = {0: "D2Q9", 1: "D3Q19", 2: "D3Q27"}
-OP_IDS = {"PR": oracle.PR, "IR": oracle.IR, "PRI": oracle.PRI}
+OP_IDS = {"PR": oracle.PR, "IR": oracle.IR, "PRI": oracle.PRI, "IRHB": oracle.IRHB}
 
 
 def perm_lib_from_oracle(lat):
@@ -38,7 +38,7 @@ def random_mask(N, seed, fraction):
 
 def run_pair(lat, dims, periodic, op, steps, *, nu_p=0.1, sigma_y=5e-4, m=1e4, g=(2e-5, -1e-5, 5e-6),
              lam=0.25, scheme="AA", precision="FP64", mask=None, seed=1, amp=1e-2, tile=None,
-             gpu_kw=None, flow_axis=0, mrt_bulk=0.0, mrt_even=0.0, pull_form=None):
+             gpu_kw=None, flow_axis=0, mrt_bulk=0.0, mrt_even=0.0, pull_form=None, hb_n=1.0):
     """Run the oracle and the library from the same seeded state; return both
     moment sets (and the populations read back)."""
     from paper_1610_01388_amd import lbm
@@ -48,7 +48,7 @@ def run_pair(lat, dims, periodic, op, steps, *, nu_p=0.1, sigma_y=5e-4, m=1e4, g
     if mask is not None:
         P0 = P0 * (1 - mask)[None, :]
     rh = oracle.rheology(OP_IDS[op], nu_p, sigma_y, m, 1e-8, lam, g, flow_axis=flow_axis, mrt_bulk=mrt_bulk,
-                         mrt_even=mrt_even)
+                         mrt_even=mrt_even, hb_n=hb_n)
     od = oracle.Domain(lat, dims, periodic, rh, mask)
     od.set_state(P0, tau0)
     od.step(steps)
@@ -58,6 +58,7 @@ def run_pair(lat, dims, periodic, op, steps, *, nu_p=0.1, sigma_y=5e-4, m=1e4, g
     perm = perm_lib_from_oracle(lat)
     dom = lbm.Domain(LAT_NAMES[lat], dims, periodic, op, nu_p, sigma_y, m=m, g=g, lambda_trt=lam,
                      precision=precision, scheme=scheme, flow_axis=flow_axis, mrt_bulk=mrt_bulk, mrt_even=mrt_even,
+                     hb_n=hb_n,
                      **(gpu_kw or {}))
     if mask is not None:
         dom.set_mask(mask)

@@ -153,6 +153,20 @@ def test_implicit_pr_needs_no_tau_and_batches_reject_it():
     assert e.value.code == -1
 
 
+def test_irhb_validation_and_batches_reject_it():
+    for n in (0.1, 6.0):
+        with pytest.raises(lbm.LbmError):
+            lbm.lbm_create(_desc(), lbm.make_rheology("IRHB", 0.01, 1e-4, hb_n=n))
+    with pytest.raises(lbm.LbmError):
+        lbm.lbm_create(_desc(), lbm.make_rheology("IRHB", 0.01, 1e-4, hb_n=0.5, mrt_even=1.2))
+    h = lbm.lbm_create(_desc(), lbm.make_rheology("IRHB", 0.01, 1e-4, hb_n=0.5))
+    lbm.lbm_destroy(h)
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_batch_query_sizes([lbm.make_desc("D3Q19", (8, 8, 4), (0, 0, 1), "FP32", "AA")],
+                                  [lbm.make_rheology("IRHB", 0.01, 1e-4, hb_n=0.5)])
+    assert e.value.code == -1
+
+
 def test_batches_reject_mrt():
     with pytest.raises(lbm.LbmError) as e:
         lbm.lbm_batch_query_sizes([lbm.make_desc("D3Q19", (8, 8, 4), (0, 0, 1), "FP32", "AA")],
