@@ -364,7 +364,10 @@ def main():
         case_pri = dict(case_pr, op="PRI")
         pri, _ = run_form(torch, lbm, "PRI FP64 (implicit tau update, no tau field)", case_pri, "FP64", mask, fluid,
                           W, K)
-        forms += [f64_ir, f64_pr, dense_ir, pri]
+        case_hb = dict(case, op="IRHB")
+        hb, _ = run_form(torch, lbm, "IRHB FP64 (Herschel-Bulkley, n = 0.5, K = nu_p)", case_hb, "FP64", mask, fluid,
+                         W, K, hb_n=0.5)
+        forms += [f64_ir, f64_pr, dense_ir, pri, hb]
         log("forms: tight medium (overlapping spheres, porosity 0.15): row-segment vs slot neighbour kernel")
         mask_t, _ = inputs.overlapping_spheres((n, n, n), 8.0, 0.15, seed=1)
         fl_t = int((mask_t == 0).sum())
