@@ -128,6 +128,51 @@ def run_form(torch, lbm, name, case, precision, mask, fluid, warmup, steps, ref=
     return out, mom
 
 
+def to_steady(dom, every=1000, tol=1e-8, cap=200_000, label=""):
+    """Step until the superficial flux changes by at most tol (relative)
+    between monitor records every steps apart, or cap steps; returns the
+    flux, the steps taken, the last relative change and the residual."""
+    dom.set_monitor_interval(every)
+    prev, steps, rel = None, 0, None
+    while steps < cap:
+        dom.step(every)
+        steps += every
+        h = dom.history()[-1]
+        q = float(h["flux"][0])
+        if prev is not None:
+            rel = abs(q - prev) / max(abs(q), 1e-300)
+            if rel <= tol:
+                break
+        prev = q
+        if steps % 20000 == 0:
+            log(f"  {label} {steps} steps, flux {q:.9e}, change {rel}")
+    return q, steps, rel, float(h["residual"])
+
+
+def darcy_sweep(torch, lbm, inputs, n, bis, ops, cap):
+    """The porous workload run to a steady Darcy flux for a range of Bingham
+    numbers, FP32 storage against FP64 (both to their own steady state)."""
+    mask, _ = inputs.sphere_pack((n, n, n), 8.0, 0.7, seed=1)
+    for op in ops:
+        for bi in bis:
+            case = inputs.porous_case(op, n=n, Bi=bi)
+            row = {"workload": f"D3Q27 {n}^3 sphere pack, porosity 0.7", "operator": op, "Bi": bi,
+                   "sigma_y": case["sigma_y"], "m": case["m"], "criterion": "flux change <= 1e-8 per 1000 steps"}
+            mom = {}
+            for prec in ("FP64", "FP32"):
+                dom = make_domain(lbm, case, prec, mask=mask)
+                t0 = time.perf_counter()
+                q, steps, rel, res = to_steady(dom, cap=cap, label=f"{op} Bi={bi} {prec}")
+                torch.cuda.synchronize()
+                row[prec] = {"flux": q, "steps": steps, "last_rel_change": rel, "residual": res,
+                             "converged": rel is not None and rel <= 1e-8, "seconds": time.perf_counter() - t0}
+                mom[prec] = dom.moments()
+                dom.close()
+                torch.cuda.empty_cache()
+            row["fp32_error_vs_fp64"] = compare(mom["FP64"], mom["FP32"], 0)
+            print(json.dumps(row), flush=True)
+
+
 def run_batch(torch, lbm, cases, precision, warmup, steps, autotune=True, graph_steps=1000):
     """The batched sweep: every case in one batch, stepped by replays of one
     captured graph of graph_steps persistent launches (one per step); tiles
@@ -270,6 +315,10 @@ def main():
                     help="only the batched sweep form (for profiling its kernel)")
     ap.add_argument("--layout", default="COMPACT", choices=["COMPACT", "DENSE"],
                     help="population storage layout of the main line")
+    ap.add_argument("--darcy", action="store_true",
+                    help="instead of the throughput line: the porous workload run to steady Darcy flux for "
+                         "Bi in {0.1, 0.316, 1, 3.16, 10}, IR and PR, FP32 against FP64 (one JSON line each)")
+    ap.add_argument("--darcy-cap", type=int, default=200_000, help="step cap of each --darcy run")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a 1 GiB device copy first (counter calibration under rocprofv3)")
     args = ap.parse_args()
@@ -281,6 +330,10 @@ def main():
     import torch
     from paper_1610_01388_amd import inputs, lbm
     torch.cuda.set_device(0)
+
+    if args.darcy:
+        darcy_sweep(torch, lbm, inputs, args.size, (0.1, 0.316, 1.0, 3.16, 10.0), ("IR", "PR"), args.darcy_cap)
+        return
 
     if args.batch_only:
         log(f"batched sweep only: warmup {args.warmup}, steps {args.steps}")
