@@ -430,6 +430,19 @@ def main():
                                  fl_t, W, K, ref=ref_t)
         forms += [tight_rows, tight_auto]
         del ref_t, mask_t
+        log("forms: A/B streaming, and the D3Q19 and D2Q9 lattices at HBM scale")
+        forms.append(run_form(torch, lbm, "IR FP64 A/B streaming (two copies)", case, "FP64", mask, fluid, W, K,
+                              ref=ref_ir, scheme="AB")[0])
+        case19 = dict(case, lattice="D3Q19")
+        forms.append(run_form(torch, lbm, "IR FP64 D3Q19, same pack", case19, "FP64", mask, fluid, W, K)[0])
+        cell = inputs.cylinder_case("IR", sigma_y=1e-5)
+        tiles = 51
+        mask2 = np.tile(cell["mask"].reshape(80, 80), (tiles, tiles)).reshape(-1)
+        case2 = dict(cell, dims=(80 * tiles, 80 * tiles, 1))
+        forms.append(run_form(torch, lbm, f"IR FP64 D2Q9, cylinder array {tiles}x{tiles} cells "
+                              f"({80 * tiles}^2, Table 2 cell)", case2, "FP64", mask2, int((mask2 == 0).sum()),
+                              W, K)[0])
+        del mask2
         log("forms: FP32 storage and collision")
         forms.append(run_form(torch, lbm, "IR FP32", case, "FP32", mask, fluid, W, K, ref=ref_ir)[0])
         forms.append(run_form(torch, lbm, "PR FP32", case_pr, "FP32", mask, fluid, W, K, ref=ref_pr)[0])
