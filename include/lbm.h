@@ -244,7 +244,8 @@ int lbm_load(lbm_domain* dom, const void* blob, size_t bytes);
 
 /* Tile shape of the step kernel: one node per thread, tx*ty*tz threads per
  * block, which must be 64, 128, 192 or 256; tz must be 1 for D2Q9; the
- * compact layout needs tx == 64 (one wavefront per 64-node row segment). */
+ * compact layout needs tx = 64, 128 or 256 (one wavefront per 64-node row
+ * segment; wider tiles hold adjacent segments of a row in one block). */
 int lbm_set_tile(lbm_domain* dom, int32_t tx, int32_t ty, int32_t tz);
 int lbm_get_tile(lbm_domain* dom, int32_t* tx, int32_t* ty, int32_t* tz);
 /* Order in which the step walks its tiles: bricks of whole rows x

@@ -249,16 +249,21 @@ __global__ __launch_bounds__(256) void k_step_compact(const StepArgs a, const ui
     if (tile >= a.ntiles) return;  // whole block leaves together
 
     const int lane = threadIdx.x & 63;
+    // A tile is tx / 64 row segments wide (so a workgroup can hold adjacent
+    // segments of one row, whose shared cache lines then meet in L2) by ty
+    // rows by tz planes; wavefront wv takes segment wv % sx of row wv / sx.
+    const int sx = a.tx >> 6;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int ly = wv % a.ty;
-    const int lz = wv / a.ty;
+    const int ly = (wv / sx) % a.ty;
+    const int lz = (wv / sx) / a.ty;
     int ttx, tty, ttz;
     tile_coords(a, tile, ttx, tty, ttz);
-    const int x0 = ttx * 64;
+    const int seg = ttx * sx + wv % sx;  // row segment = bitmap word index
+    const int x0 = seg * 64;
     const int x = x0 + lane;
     const int y = tty * a.ty + ly;
     const int z = ttz * a.tz + lz;
-    const bool wave_in = (y < a.ny) && (z < a.nz);
+    const bool wave_in = (y < a.ny) && (z < a.nz) && (x0 < a.nx);
     const int64_t St = a.S;
 
     // Neighbourhood of node x: fluid flag of x + d (bit d of nbf, d = (dx, dy,
@@ -293,10 +298,10 @@ __global__ __launch_bounds__(256) void k_step_compact(const StepArgs a, const ui
             bool lf = false, rf = false;
             if (rv) {
                 const int64_t row = ((int64_t)yy + (int64_t)a.ny * zz) * a.W;
-                mb = bits[row + ttx];
-                mbase = wbase[row + ttx];
+                mb = bits[row + seg];
+                mbase = wbase[row + seg];
                 int wl = -1, bl = 63;
-                if (x0 > 0) wl = ttx - 1;
+                if (x0 > 0) wl = seg - 1;
                 else if (a.per[0]) { wl = (a.nx - 1) >> 6; bl = (a.nx - 1) & 63; }
                 if (wl >= 0) {
                     const uint64_t lb = bits[row + wl];
@@ -304,7 +309,7 @@ __global__ __launch_bounds__(256) void k_step_compact(const StepArgs a, const ui
                     lidx = wbase[row + wl] + (uint32_t)__popcll(lb & ((1ull << bl) - 1ull));
                 }
                 int wr = -1;
-                if (x0 + 64 < a.nx) wr = ttx + 1;
+                if (x0 + 64 < a.nx) wr = seg + 1;
                 else if (a.per[0]) wr = 0;
                 if (wr >= 0) {
                     rf = bits[row + wr] & 1;

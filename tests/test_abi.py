@@ -106,6 +106,10 @@ def test_unbound_domain_refuses_work():
     with pytest.raises(lbm.LbmError):
         lbm.lbm_set_tile(h, 8, 8, 2)  # compact needs one wavefront per 64-node row segment
     lbm.lbm_set_tile(h, 64, 2, 2)
+    lbm.lbm_set_tile(h, 128, 2, 1)  # two adjacent row segments per block
+    lbm.lbm_set_tile(h, 256, 1, 1)
+    with pytest.raises(lbm.LbmError):
+        lbm.lbm_set_tile(h, 192, 1, 1)
     with pytest.raises(lbm.LbmError) as e:
         lbm.lbm_set_pull_form(h, 3)
     assert e.value.code == -1
