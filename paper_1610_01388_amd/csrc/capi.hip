@@ -233,10 +233,12 @@ int pow2ceil(int v)
 void default_tile(lbm_domain* dm)
 {
     if (dm->d.layout == LBM_COMPACT) {
-        // as many 64-node segments of one row per block as the row has (up to
-        // 4: their shared cache lines then meet in L2; 256x1x1 measured 1.5%
-        // faster than 64x4x1 on the 256^3 pack), the other waves over y, z
-        const int sx = dm->L.W >= 4 ? 4 : dm->L.W >= 2 ? 2 : 1;
+        // up to 4 adjacent 64-node segments of one row per block (their shared
+        // cache lines then meet in L2; 256x1x1 measured 1.5% faster than
+        // 64x4x1 on the 256^3 pack), the largest count that divides the row's
+        // segments so that no wavefront sits past the row end (384 wide: 2),
+        // the other waves over y, z
+        const int sx = dm->L.W % 4 == 0 ? 4 : dm->L.W % 2 == 0 ? 2 : 1;
         dm->tx = 64 * sx;
         dm->ty = std::min(pow2ceil(dm->d.ny), 4 / sx);
         dm->tz = dm->D == 3 ? std::min(pow2ceil(dm->d.nz), 4 / (sx * dm->ty)) : 1;
