@@ -921,9 +921,11 @@ int lbm_autotune(lbm_domain* dm, int32_t trial_steps)
     if ((rc = lbm_save(dm, saved.data(), &bytes))) return rc;
     const int mon_k = dm->mon_k;
     dm->mon_k = 0;
-    hipEvent_t e0, e1;
-    HIPCHK(hipEventCreate(&e0));
-    HIPCHK(hipEventCreate(&e1));
+    // Every exit below restores the monitor interval, tile and kernel form
+    // and reloads the saved state; a HIP error is reported after that.
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t he = hipEventCreate(&e0);
+    if (he == hipSuccess) he = hipEventCreate(&e1);
     static const int candc3[][3] = {{64, 4, 1}, {64, 2, 2}, {64, 1, 4}, {128, 2, 1}, {128, 1, 2}, {256, 1, 1},
                                     {64, 2, 1}, {64, 1, 2}, {64, 1, 1}};
     static const int candc2[][3] = {{64, 4, 1}, {128, 2, 1}, {256, 1, 1}, {64, 2, 1}, {64, 1, 1}};
@@ -940,7 +942,7 @@ int lbm_autotune(lbm_domain* dm, int32_t trial_steps)
     float best_ms = 1e30f;
     const int keep[3] = {dm->tx, dm->ty, dm->tz};
     const int keep_form = dm->pull_form;
-    for (int c = dm->d.layout == LBM_COMPACT ? -1 : 0; c < nc; ++c) {
+    for (int c = dm->d.layout == LBM_COMPACT ? -1 : 0; c < nc && he == hipSuccess; ++c) {
         if (c >= 0) {
             const int tx = cand[c][0], ty = cand[c][1], tz = cand[c][2];
             if (check_tile(dm, tx, ty, tz) != LBM_OK) continue;
@@ -951,31 +953,33 @@ int lbm_autotune(lbm_domain* dm, int32_t trial_steps)
         }
         dm->pull_form = c < 0 ? LBM_PULL_SLOTS : LBM_PULL_ROWS;
         if ((rc = run_steps(dm, 2))) break;
-        HIPCHK(hipEventRecord(e0, dm->stream));
+        if ((he = hipEventRecord(e0, dm->stream)) != hipSuccess) break;
         if ((rc = run_steps(dm, trial_steps))) break;
-        HIPCHK(hipEventRecord(e1, dm->stream));
-        HIPCHK(hipEventSynchronize(e1));
+        if ((he = hipEventRecord(e1, dm->stream)) != hipSuccess) break;
+        if ((he = hipEventSynchronize(e1)) != hipSuccess) break;
         float ms = 0;
-        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        if ((he = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
         if (ms < best_ms) {
             best_ms = ms;
             best = c;
         }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
     dm->mon_k = mon_k;
     dm->tx = keep[0];
     dm->ty = keep[1];
     dm->tz = keep[2];
     dm->pull_form = keep_form;
-    if (best >= 0) {
+    const bool ok = rc == LBM_OK && he == hipSuccess;
+    if (ok && best >= 0) {
         dm->tx = cand[best][0];
         dm->ty = cand[best][1];
         dm->tz = cand[best][2];
     }
-    if (best >= -1 && dm->d.layout == LBM_COMPACT) dm->pull_form = best < 0 ? LBM_PULL_SLOTS : LBM_PULL_ROWS;
+    if (ok && best >= -1 && dm->d.layout == LBM_COMPACT) dm->pull_form = best < 0 ? LBM_PULL_SLOTS : LBM_PULL_ROWS;
     const int rc_load = lbm_load(dm, saved.data(), bytes);
+    if (he != hipSuccess) return fail(LBM_EHIP, "autotune: %s", hipGetErrorString(he));
     if (rc) return rc;
     return rc_load;
 }
@@ -1575,35 +1579,42 @@ int lbm_batch_autotune(lbm_batch* b, int32_t trial_steps)
     const int64_t t = b->t;
     const auto times = b->mon_times;
     b->mon_k = 0;
-    hipEvent_t e0, e1;
-    HIPCHK(hipEventCreate(&e0));
-    HIPCHK(hipEventCreate(&e1));
+    // A HIP error stops the trials; the schedule, the state and the monitor
+    // settings are restored below before it is reported.
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t he = hipEventCreate(&e0);
+    if (he == hipSuccess) he = hipEventCreate(&e1);
     int best = keep;
     float best_ms = 1e30f;
     // candidates: tile policy x work-item order
-    for (int cand = 0; cand < 2 * kBatchPolicies && rc == LBM_OK; ++cand) {
+    for (int cand = 0; cand < 2 * kBatchPolicies && rc == LBM_OK && he == hipSuccess; ++cand) {
         b->policy = cand % kBatchPolicies;
         b->xcd = cand / kBatchPolicies;
         if ((rc = batch_plan(b))) break;
-        HIPCHK(hipMemcpy(b->workbuf + b->L.sims, b->sims.data(), sizeof(BatchSim) * b->count, hipMemcpyHostToDevice));
-        HIPCHK(hipMemcpy(b->workbuf + b->L.work_list, b->work.data(), sizeof(int) * b->nitems, hipMemcpyHostToDevice));
+        if ((he = hipMemcpy(b->workbuf + b->L.sims, b->sims.data(), sizeof(BatchSim) * b->count,
+                            hipMemcpyHostToDevice)) != hipSuccess)
+            break;
+        if ((he = hipMemcpy(b->workbuf + b->L.work_list, b->work.data(), sizeof(int) * b->nitems,
+                            hipMemcpyHostToDevice)) != hipSuccess)
+            break;
         batch_set_grid(b);
         int par = b->parity;
         int64_t tt = b->t;
         if ((rc = batch_enqueue(b, 2, b->stream, par, tt, false))) break;
-        HIPCHK(hipEventRecord(e0, b->stream));
+        if ((he = hipEventRecord(e0, b->stream)) != hipSuccess) break;
         if ((rc = batch_enqueue(b, trial_steps, b->stream, par, tt, false))) break;
-        HIPCHK(hipEventRecord(e1, b->stream));
-        HIPCHK(hipEventSynchronize(e1));
+        if ((he = hipEventRecord(e1, b->stream)) != hipSuccess) break;
+        if ((he = hipEventSynchronize(e1)) != hipSuccess) break;
         float ms = 0;
-        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        if ((he = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
         if (ms < best_ms) {
             best_ms = ms;
             best = cand;
         }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (rc != LBM_OK || he != hipSuccess) best = keep;
     b->policy = best % kBatchPolicies;
     b->xcd = best / kBatchPolicies;
     int rc2 = batch_plan(b);
@@ -1619,6 +1630,7 @@ int lbm_batch_autotune(lbm_batch* b, int32_t trial_steps)
     b->mon_k = mon_k;
     b->mon_times = times;
     batch_drop_graph(b);
+    if (he != hipSuccess) return fail(LBM_EHIP, "batch autotune: %s", hipGetErrorString(he));
     return rc ? rc : rc2;
 }
 
