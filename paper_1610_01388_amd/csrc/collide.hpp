@@ -72,8 +72,10 @@ __device__ __forceinline__ void add_c(C& acc, C v, int c)
 }
 
 // Eq. 9: zeroth, first and second moments (of the deviations).
-template <int LAT, class C>
-__device__ __forceinline__ Moments<C> moments(const C (&h)[Lattice<LAT>::Q])
+// Accumulated in C from populations stored as H (the FP64 redo of a
+// reduced-precision node sums its float values in double, no double copy).
+template <int LAT, class C, class H>
+__device__ __forceinline__ Moments<C> moments_as(const H (&h)[Lattice<LAT>::Q])
 {
     using L = Lattice<LAT>;
     Moments<C> mo;
@@ -84,7 +86,7 @@ __device__ __forceinline__ Moments<C> moments(const C (&h)[Lattice<LAT>::Q])
     for (int a = 0; a < 6; ++a) mo.p[a] = 0;
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
-        const C v = h[i];
+        const C v = (C)h[i];
         mo.drho += v;
         add_c<LAT>(mo.j[0], v, L::cx[i]);
         add_c<LAT>(mo.j[1], v, L::cy[i]);
@@ -97,6 +99,12 @@ __device__ __forceinline__ Moments<C> moments(const C (&h)[Lattice<LAT>::Q])
         add_c<LAT>(mo.p[5], v, L::cy[i] * L::cz[i]);
     }
     return mo;
+}
+
+template <int LAT, class C>
+__device__ __forceinline__ Moments<C> moments(const C (&h)[Lattice<LAT>::Q])
+{
+    return moments_as<LAT, C, C>(h);
 }
 
 // Non-equilibrium second moment Pi - rho cs^2 I - rho v v, from the
@@ -316,8 +324,10 @@ __device__ __forceinline__ Pre<C> rheology(const Moments<C>& mo, const Coll<C>& 
 //   f_eq(u + g) - f_eq(u) written out (Sec. 2.4, Eq. 34).
 //  IR: f_eq(u) + f_sigma + Phi/2 with f_sigma = w/(2 cs^4)(c c - cs^2 I):A
 //   and Phi = 3 w c.F, F = rho g (Sec. 2.3 Eqs. 28-29, Sec. 2.4 Eq. 35).
-template <int LAT, int OP, class C>
-__device__ __forceinline__ void relax(C (&h)[Lattice<LAT>::Q], const Moments<C>& mo, const Pre<C>& r,
+// Computed in C, read from and written to populations stored as H (H = C
+// except in the FP64 redo of a reduced-precision node).
+template <int LAT, int OP, class C, class H>
+__device__ __forceinline__ void relax(H (&h)[Lattice<LAT>::Q], const Moments<C>& mo, const Pre<C>& r,
                                       const Coll<C>& p)
 {
     using L = Lattice<LAT>;
@@ -343,9 +353,10 @@ __device__ __forceinline__ void relax(C (&h)[Lattice<LAT>::Q], const Moments<C>&
         {  // rest velocity: symmetric only (f2d = 0, f2b = -cs^2 d trd * 9/2 w = -1.5 w d trd)
             const C w = C(L::w[0]);
             const C es = w * (mo.drho - C(1.5) * r.rho * uu);
-            C ns0 = om_e * (h[0] - es);
+            const C h0 = (C)h[0];
+            C ns0 = om_e * (h0 - es);
             if (mrt) ns0 += dbu * (C(-1.5) * w * C(D) * trd);
-            h[0] = h[0] - ns0 - C(1.5) * r.rho * w * ug;
+            h[0] = (H)(h0 - ns0 - C(1.5) * r.rho * w * ug);
         }
 #pragma unroll
         for (int i = 1; i < L::Q; i += 2) {
@@ -360,8 +371,9 @@ __device__ __forceinline__ void relax(C (&h)[Lattice<LAT>::Q], const Moments<C>&
             add_c<LAT>(cg, p.g[2], L::cz[i]);
             const C es = w * (mo.drho + r.rho * (C(4.5) * cu * cu - C(1.5) * uu));
             const C ea = C(3) * w * r.rho * cu;
-            const C hs = C(0.5) * (h[i] + h[k]);
-            const C ha = C(0.5) * (h[i] - h[k]);
+            const C hi = (C)h[i], hk = (C)h[k];
+            const C hs = C(0.5) * (hi + hk);
+            const C ha = C(0.5) * (hi - hk);
             C ns = om_e * (hs - es);
             if (mrt) {
                 C cpc = 0;  // c c : Pi_neq
@@ -380,8 +392,8 @@ __device__ __forceinline__ void relax(C (&h)[Lattice<LAT>::Q], const Moments<C>&
             // f_eq(u+g) - f_eq(u) for +c and -c
             const C fs = r.rho * w * (C(4.5) * cg * (C(2) * cu + cg) - C(1.5) * ug);
             const C fa = r.rho * w * C(3) * cg;
-            h[i] = h[i] - ns - na + fs + fa;
-            h[k] = h[k] - ns + na + fs - fa;
+            h[i] = (H)(hi - ns - na + fs + fa);
+            h[k] = (H)(hk - ns + na + fs - fa);
         }
     } else {
         const C* A = r.a;
@@ -405,7 +417,7 @@ __device__ __forceinline__ void relax(C (&h)[Lattice<LAT>::Q], const Moments<C>&
             add_c<LAT>(cac, C(2) * A[4], L::cx[i] * L::cz[i]);
             add_c<LAT>(cac, C(2) * A[5], L::cy[i] * L::cz[i]);
             const C heq = w * (mo.drho + r.rho * (C(3) * cu + C(4.5) * cu * cu - C(1.5) * uu));
-            h[i] = heq + C(4.5) * w * (cac - trA * third) + C(1.5) * w * r.rho * cg;
+            h[i] = (H)(heq + C(4.5) * w * (cac - trA * third) + C(1.5) * w * r.rho * cg);
         }
     }
 }

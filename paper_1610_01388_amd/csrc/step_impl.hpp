@@ -31,14 +31,11 @@ __device__ __forceinline__ void collide_node(typename Store<PREC>::C (&h)[Lattic
     pr = rheology<LAT, OP>(mo, cp, tau_prev);
     if constexpr (PREC != PREC_F64 && (OP & OP_FB) != 0) {
         if (fallback && pr.near_yield) {
-            double hd[Q];
-#pragma unroll
-            for (int i = 0; i < Q; ++i) hd[i] = (double)h[i];
-            const Moments<double> md = moments<LAT>(hd);
+            // FP64 from the stored values (exact in double), straight back
+            // into h: no double copy of the populations is held
+            const Moments<double> md = moments_as<LAT, double>(h);
             const Pre<double> pd = rheology<LAT, OP>(md, cd, (double)tau_prev);
-            relax<LAT, OP>(hd, md, pd, cd);
-#pragma unroll
-            for (int i = 0; i < Q; ++i) h[i] = (C)hd[i];
+            relax<LAT, OP>(h, md, pd, cd);
             pr.tau_p = (C)pd.tau_p;
             pr.unyielded = pd.unyielded;
             used_fb = true;
