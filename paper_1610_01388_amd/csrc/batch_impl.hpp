@@ -1,7 +1,8 @@
 // batch_impl.hpp -- the batched step: many independent all-fluid domains
 // (walls only through non-periodic axes) advanced by one launch per time
 // step.  Every simulation is cut into tiles of 256 nodes; a work item is one
-// tile, so items are equally sized whatever the simulation's size.  A
+// tile (in the AA local phase, 256 consecutive nodes), so items are equally
+// sized whatever the simulation's size.  A
 // persistent grid walks the work list; each item reads its simulation's
 // sizes, tile shape, operator and parameters from a device table (wave-
 // uniform, scalar loads), so mixed operators branch per item, not per lane.
@@ -15,9 +16,11 @@
 
 namespace lbm {
 
+// Neighbour phase (AA pull) of one tile.
 template <int LAT, int OP, int PREC, int PAT, bool MON>
 __device__ __forceinline__ void batch_tile(const BatchArgs& a, const BatchSim& sm, int item)
 {
+    static_assert(PAT == PAT_AB || PAT == PAT_AA_PULL, "neighbour phases only");
     using L = Lattice<LAT>;
     constexpr int Q = L::Q;
     using S = typename Store<PREC>::S;
@@ -72,15 +75,11 @@ __device__ __forceinline__ void batch_tile(const BatchArgs& a, const BatchSim& s
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
             int idx;
-            if constexpr (PAT == PAT_AA_LOCAL) {
-                idx = i * N + n;
-            } else {
-                const int s = nb(-L::cx[i], -L::cy[i], -L::cz[i]);
-                if constexpr (PAT == PAT_AB)
-                    idx = s >= 0 ? i * N + s : opp(i) * N + n;
-                else
-                    idx = s >= 0 ? opp(i) * N + s : i * N + n;
-            }
+            const int s = nb(-L::cx[i], -L::cy[i], -L::cz[i]);
+            if constexpr (PAT == PAT_AB)
+                idx = s >= 0 ? i * N + s : opp(i) * N + n;
+            else
+                idx = s >= 0 ? opp(i) * N + s : i * N + n;
             h[i] = decode<PREC>(A[idx], L::w[i], a.h16_scale);
         }
         T* tau = (T*)a.tau + sm.off_tau;
@@ -95,14 +94,58 @@ __device__ __forceinline__ void batch_tile(const BatchArgs& a, const BatchSim& s
             int idx;
             if constexpr (PAT == PAT_AB) {
                 idx = i * N + n;  // A/B is not offered for batches; kept for completeness
-            } else if constexpr (PAT == PAT_AA_LOCAL) {
-                idx = opp(i) * N + n;
             } else {
                 const int d = nb(L::cx[i], L::cy[i], L::cz[i]);
                 idx = d >= 0 ? i * N + d : opp(i) * N + n;
             }
             B[idx] = encode<PREC>(h[i], L::w[i], a.h16_inv);
         }
+        if constexpr (has_tau(OP)) tau[n] = (T)pr.tau_p;
+    }
+    if constexpr (MON)
+        monitor_block<C>(active, mo, pr, cp, used_fb, a.partials + (int64_t)item * MP_COUNT,
+                         a.uprev ? a.uprev + sm.off_u : nullptr, n, N);
+}
+
+// AA local phase of one item.  This half of the AA pair touches only the
+// node's own slots, so an item names 256 consecutive nodes instead of a tile
+// (a simulation has at least ceil(N / 256) items; the surplus ones are
+// empty) and each direction is one contiguous run per wavefront.  Ordinary
+// loads and stores: with non-temporal hints this phase measured slower.
+template <int LAT, int OP, int PREC, bool MON>
+__device__ __forceinline__ void batch_local(const BatchArgs& a, const BatchSim& sm, int item)
+{
+    using L = Lattice<LAT>;
+    constexpr int Q = L::Q;
+    using S = typename Store<PREC>::S;
+    using C = typename Store<PREC>::C;
+    using T = typename Store<PREC>::T;
+
+    const int N = (int)sm.N;  // Q * N < 2^31 is checked on the host
+    const int n = (item - sm.item0) * 256 + (int)threadIdx.x;
+    const bool active = n < N;
+    const Coll<C>& cp = [&]() -> const Coll<C>& {
+        if constexpr (PREC == PREC_F64) return sm.cd;
+        else return sm.cf;
+    }();
+
+    Moments<C> mo;
+    Pre<C> pr;
+    bool used_fb = false;
+    if (active) {
+        const S* A = (const S*)a.pdf + sm.off_pdf;
+        C h[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) h[i] = decode<PREC>(A[i * N + n], L::w[i], a.h16_scale);
+        T* tau = (T*)a.tau + sm.off_tau;
+        C tau_prev = C(0);
+        if constexpr (has_tau(OP)) tau_prev = (C)tau[n];
+
+        collide_node<LAT, OP, PREC>(h, tau_prev, a.fallback, sm.cd, cp, mo, pr, used_fb);
+
+        S* B = (S*)a.pdf + sm.off_pdf;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) B[opp(i) * N + n] = encode<PREC>(h[i], L::w[i], a.h16_inv);
         if constexpr (has_tau(OP)) tau[n] = (T)pr.tau_p;
     }
     if constexpr (MON)
@@ -134,8 +177,13 @@ __global__ __launch_bounds__(256) void k_batch_step(const BatchArgs a)
         const BatchSim& sm = a.sims[sim];
         // PR or IR (the host rejects PRI for batches: its Newton solve would
         // raise the register count of this shared kernel for every item)
-        if (sm.op == OP_PR) batch_tile<LAT, OP_PR | F, PREC, PAT, MON>(a, sm, item);
-        else batch_tile<LAT, OP_IR | F, PREC, PAT, MON>(a, sm, item);
+        if constexpr (PAT == PAT_AA_LOCAL) {
+            if (sm.op == OP_PR) batch_local<LAT, OP_PR | F, PREC, MON>(a, sm, item);
+            else batch_local<LAT, OP_IR | F, PREC, MON>(a, sm, item);
+        } else {
+            if (sm.op == OP_PR) batch_tile<LAT, OP_PR | F, PREC, PAT, MON>(a, sm, item);
+            else batch_tile<LAT, OP_IR | F, PREC, PAT, MON>(a, sm, item);
+        }
         // the block reduction's LDS slots are read by thread 0 after its
         // barrier; the next item must not overwrite them before that
         if constexpr (MON) __syncthreads();
