@@ -320,9 +320,11 @@ int lbm_batch_time(lbm_batch* b, int64_t* t);
 /* Tile shape chosen for each simulation (3*count ints). */
 int lbm_batch_get_tiles(lbm_batch* b, int32_t* tiles);
 /* Scheduling in use: tile policy (0 fewest padded nodes, 1 rows at least
- * 64 wide, 2 fixed 64x4x1) and work-item order (0 plain grid stride over
- * the list; 1, the default, one contiguous chunk of the list per XCD so
- * that neighbouring tiles share an L2). */
+ * 64 wide, 2 fixed 64x4x1, 3, the default, runs of 256 consecutive nodes in
+ * node order, rows wrapping, reported by lbm_batch_get_tiles as 256x1x1) and
+ * work-item order (0, the default, plain grid stride over the list; 1 one
+ * contiguous chunk of the list per XCD so that neighbouring tiles share an
+ * L2). */
 int lbm_batch_get_schedule(lbm_batch* b, int32_t* tile_policy, int32_t* xcd_order);
 /* Choose the scheduling by hand (the state is kept; results do not depend on
  * it).  LBM_EINVAL outside the ranges above.  Synchronises. */

@@ -29,17 +29,27 @@ __device__ __forceinline__ void batch_tile(const BatchArgs& a, const BatchSim& s
 
     const int tile = item - sm.item0;
     const int t = threadIdx.x;
-    const int lx = t % sm.tx;
-    const int lyz = t / sm.tx;
-    const int ly = lyz % sm.ty;
-    const int lz = lyz / sm.ty;
-    const int ttx = tile % sm.ntx;
-    const int trem = tile / sm.ntx;
-    const int tty = trem % sm.nty;
-    const int ttz = trem / sm.nty;
-    const int x = ttx * sm.tx + lx;
-    const int y = tty * sm.ty + ly;
-    const int z = ttz * sm.tz + lz;
+    int x, y, z;
+    if (sm.linear) {
+        // the item is a run of 256 consecutive nodes (rows wrap)
+        const int m = tile * 256 + t;
+        const int r = m / sm.nx;
+        x = m - r * sm.nx;
+        y = r % sm.ny;
+        z = r / sm.ny;
+    } else {
+        const int lx = t % sm.tx;
+        const int lyz = t / sm.tx;
+        const int ly = lyz % sm.ty;
+        const int lz = lyz / sm.ty;
+        const int ttx = tile % sm.ntx;
+        const int trem = tile / sm.ntx;
+        const int tty = trem % sm.nty;
+        const int ttz = trem / sm.nty;
+        x = ttx * sm.tx + lx;
+        y = tty * sm.ty + ly;
+        z = ttz * sm.tz + lz;
+    }
     const bool active = (x < sm.nx) & (y < sm.ny) & (z < sm.nz);
     // indices inside one simulation fit 32 bits (Q * N < 2^31 is checked on
     // the host)

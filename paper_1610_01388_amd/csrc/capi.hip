@@ -1030,8 +1030,9 @@ struct lbm_batch {
     hipGraphExec_t graph = nullptr;
     int graph_for_mon = -1;
     int grid = 0;
-    int policy = 0;  // tile policy: 0 fewest padded nodes (wide rows on ties), 1 prefer 64-wide rows, 2 fixed 64x4x1
-    int xcd = 1;     // work-item order: 1 = one contiguous chunk per XCD, 0 = plain grid stride
+    int policy = 3;  // tile policy: 0 fewest padded nodes (wide rows on ties), 1 prefer 64-wide rows, 2 fixed 64x4x1,
+                     // 3 (default) runs of 256 consecutive nodes
+    int xcd = 0;     // work-item order: 1 = one contiguous chunk per XCD, 0 (default) = plain grid stride
     size_t bound_total = 0;  // work-buffer bytes the layout had when bound
 };
 
@@ -1045,6 +1046,7 @@ void tile_for(const lbm_desc& d, int D, int policy, int& tx, int& ty, int& tz)
     const int (*c)[3] = D == 3 ? c3 : c2;
     const int nc = D == 3 ? 9 : 7;
     if (policy == 2) { tx = 64; ty = 4; tz = 1; return; }
+    if (policy == 3) { tx = 256; ty = 1; tz = 1; return; }  // node runs: rows wrap, reported as 256 x 1 x 1
     int64_t best = -1;
     for (int k = 0; k < nc; ++k) {
         if (policy == 1 && c[k][0] < 64) continue;
@@ -1054,10 +1056,11 @@ void tile_for(const lbm_desc& d, int D, int policy, int& tx, int& ty, int& tz)
     }
 }
 
-constexpr int kBatchPolicies = 3;
+constexpr int kBatchPolicies = 4;
 
 int64_t tiles_of(const lbm_desc& d, int D, int policy)
 {
+    if (policy == 3) return ((int64_t)d.nx * d.ny * d.nz + 255) / 256;
     int tx = 0, ty = 0, tz = 0;
     tile_for(d, D, policy, tx, ty, tz);
     return (int64_t)((d.nx + tx - 1) / tx) * ((d.ny + ty - 1) / ty) * ((d.nz + tz - 1) / tz);
@@ -1079,9 +1082,10 @@ int batch_plan(lbm_batch* b)
         if (b->D == 2) s.per[2] = 1;
         s.op = b->r[k].op;
         tile_for(d, b->D, b->policy, s.tx, s.ty, s.tz);
-        s.ntx = (d.nx + s.tx - 1) / s.tx;
-        s.nty = (d.ny + s.ty - 1) / s.ty;
-        s.ntz = (d.nz + s.tz - 1) / s.tz;
+        s.linear = b->policy == 3 ? 1 : 0;
+        s.ntx = s.linear ? (int)tiles_of(d, b->D, 3) : (d.nx + s.tx - 1) / s.tx;
+        s.nty = s.linear ? 1 : (d.ny + s.ty - 1) / s.ty;
+        s.ntz = s.linear ? 1 : (d.nz + s.tz - 1) / s.tz;
         const int64_t items = (int64_t)s.ntx * s.nty * s.ntz;
         if ((int64_t)b->work.size() + items > INT32_MAX) return fail(LBM_EINVAL, "batch too large");
         s.item0 = (int)b->work.size();

@@ -115,7 +115,7 @@ struct BatchSim {
     int tx, ty, tz;        // tile shape (tx*ty*tz == 256)
     int ntx, nty, ntz;
     int item0, nitems;     // this simulation's work items [item0, item0 + nitems)
-    int pad_;
+    int linear;            // 1: items are runs of 256 consecutive nodes (rows wrap) instead of tiles
     int64_t N;             // nodes
     int64_t off_pdf;       // element offset of the simulation's population block ([i][n], stride N)
     int64_t off_tau;       // element offset of its relaxation-time block (PR)
