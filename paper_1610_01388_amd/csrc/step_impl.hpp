@@ -240,6 +240,12 @@ __global__ __launch_bounds__(256) void k_step_compact(const StepArgs a, const ui
     using S = typename Store<PREC>::S;
     using C = typename Store<PREC>::C;
     using T = typename Store<PREC>::T;
+    // SEL: neighbour addresses by selecting a 32-bit slot and one of two
+    // wave-uniform array bases (no branch, fewer registers: more waves per
+    // SIMD for the FP64 operators with a per-node solve or a tau field);
+    // otherwise one 64-bit index per direction, which the compiler turns
+    // into branches but which measured faster for IR and reduced precision.
+    constexpr bool SEL = PREC == PREC_F64 && op_base(OP) != OP_IR;
 
     const int b = blockIdx.x;
     const int tile = (b & 7) * a.tiles_per_xcd + (b >> 3);
@@ -347,18 +353,21 @@ __global__ __launch_bounds__(256) void k_step_compact(const StepArgs a, const ui
         const S* A = (const S*)a.src;
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            int64_t idx;
+            const S* p;
             if constexpr (PAT == PAT_AA_LOCAL) {
-                idx = (int64_t)i * St + k;
+                p = A + (int64_t)i * St + k;
             } else {
                 const int r = (1 - L::cy[i]) + 3 * (1 - L::cz[i]);  // row of x - c_i
                 const bool fl = (nbf >> (3 * r + 1 - L::cx[i])) & 1;
-                if constexpr (PAT == PAT_AB)
-                    idx = fl ? (int64_t)i * St + nbi(-L::cx[i], r) : (int64_t)opp(i) * St + k;
-                else
-                    idx = fl ? (int64_t)opp(i) * St + nbi(-L::cx[i], r) : (int64_t)i * St + k;
+                const int dn = PAT == PAT_AB ? i : opp(i), db = PAT == PAT_AB ? opp(i) : i;
+                if constexpr (SEL) {
+                    const uint32_t sl = fl ? nbi(-L::cx[i], r) : (uint32_t)k;
+                    p = (fl ? A + dn * St : A + db * St) + sl;
+                } else {
+                    p = A + (fl ? (int64_t)dn * St + nbi(-L::cx[i], r) : (int64_t)db * St + k);
+                }
             }
-            h[i] = decode<PREC>(A[idx], L::w[i], a.h16_scale);
+            h[i] = decode<PREC>(*p, L::w[i], a.h16_scale);
         }
         if constexpr (has_tau(OP)) tau_prev = (C)((const T*)a.tau)[k];
 
@@ -372,21 +381,27 @@ __global__ __launch_bounds__(256) void k_step_compact(const StepArgs a, const ui
             // history from the optimiser; it emits no instruction.
 #pragma unroll
             for (int r = 0; r < 9; ++r) asm volatile("" : "+v"(im[r]));
+            if constexpr (SEL) asm volatile("" : "+v"(nbf));
         }
         S* B = (S*)a.dst;
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            int64_t idx;
+            S* p;
             if constexpr (PAT == PAT_AB) {
-                idx = (int64_t)i * St + k;
+                p = B + (int64_t)i * St + k;
             } else if constexpr (PAT == PAT_AA_LOCAL) {
-                idx = (int64_t)opp(i) * St + k;
+                p = B + (int64_t)opp(i) * St + k;
             } else {
                 const int r = (1 + L::cy[i]) + 3 * (1 + L::cz[i]);  // row of x + c_i
                 const bool fl = (nbf >> (3 * r + 1 + L::cx[i])) & 1;
-                idx = fl ? (int64_t)i * St + nbi(L::cx[i], r) : (int64_t)opp(i) * St + k;
+                if constexpr (SEL) {
+                    const uint32_t sl = fl ? nbi(L::cx[i], r) : (uint32_t)k;
+                    p = (fl ? B + i * St : B + opp(i) * St) + sl;
+                } else {
+                    p = B + (fl ? (int64_t)i * St + nbi(L::cx[i], r) : (int64_t)opp(i) * St + k);
+                }
             }
-            B[idx] = encode<PREC>(h[i], L::w[i], a.h16_inv);
+            *p = encode<PREC>(h[i], L::w[i], a.h16_inv);
         }
         if constexpr (has_tau(OP)) ((T*)a.tau)[k] = (T)pr.tau_p;
     }
@@ -576,12 +591,9 @@ __global__ __launch_bounds__(256) void k_pull_slots(const StepArgs a)
         for (int i = 0; i < Q; ++i) {
             const int r = (1 - L::cy[i]) + 3 * (1 - L::cz[i]);  // row of x - c_i
             const bool fl = (nbf >> (3 * r + 1 - L::cx[i])) & 1;
-            int64_t idx;
-            if constexpr (PAT == PAT_AB)
-                idx = fl ? (int64_t)i * St + nbi(-L::cx[i], r) : (int64_t)opp(i) * St + k;
-            else
-                idx = fl ? (int64_t)opp(i) * St + nbi(-L::cx[i], r) : (int64_t)i * St + k;
-            h[i] = decode<PREC>(A[idx], L::w[i], a.h16_scale);
+            const int dn = PAT == PAT_AB ? i : opp(i), db = PAT == PAT_AB ? opp(i) : i;
+            const uint32_t sl = fl ? nbi(-L::cx[i], r) : (uint32_t)k;
+            h[i] = decode<PREC>((fl ? A + dn * St : A + db * St)[sl], L::w[i], a.h16_scale);
         }
         if constexpr (has_tau(OP)) tau_prev = (C)((const T*)a.tau)[k];
 
@@ -600,15 +612,16 @@ __global__ __launch_bounds__(256) void k_pull_slots(const StepArgs a)
         S* B = (S*)a.dst;
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            int64_t idx;
+            S* p;
             if constexpr (PAT == PAT_AB) {
-                idx = (int64_t)i * St + k;
+                p = B + (int64_t)i * St + k;
             } else {
                 const int r = (1 + L::cy[i]) + 3 * (1 + L::cz[i]);  // row of x + c_i
                 const bool fl = (nbf >> (3 * r + 1 + L::cx[i])) & 1;
-                idx = fl ? (int64_t)i * St + nbi(L::cx[i], r) : (int64_t)opp(i) * St + k;
+                const uint32_t sl = fl ? nbi(L::cx[i], r) : (uint32_t)k;
+                p = (fl ? B + i * St : B + opp(i) * St) + sl;
             }
-            B[idx] = encode<PREC>(h[i], L::w[i], a.h16_inv);
+            *p = encode<PREC>(h[i], L::w[i], a.h16_inv);
         }
         if constexpr (has_tau(OP)) ((T*)a.tau)[k] = (T)pr.tau_p;
     }
