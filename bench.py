@@ -430,6 +430,9 @@ def main():
                                  fl_t, W, K, ref=ref_t)
         forms += [tight_rows, tight_auto]
         del ref_t, mask_t
+        log("forms: all-fluid periodic box of the same size (ceiling of this access pattern)")
+        forms.append(run_form(torch, lbm, "IR FP64 all-fluid periodic box (ceiling)", case, "FP64",
+                              np.zeros(n ** 3, dtype=np.uint8), n ** 3, W, K)[0])
         log("forms: A/B streaming, and the D3Q19 and D2Q9 lattices at HBM scale")
         forms.append(run_form(torch, lbm, "IR FP64 A/B streaming (two copies)", case, "FP64", mask, fluid, W, K,
                               ref=ref_ir, scheme="AB")[0])
