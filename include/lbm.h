@@ -280,7 +280,8 @@ int lbm_destroy(lbm_domain* dom);
  * share one lattice, one precision, the AA scheme, the FP64-fallback flag
  * and the FP16 scale; each holds fewer than 2^31 / Q nodes and uses LBM_PR
  * or LBM_IR.  One step is one persistent kernel launch over a work
- * list of 256-node tiles of all simulations; lbm_batch_step replays a
+ * list of 256-node items of all simulations (runs of consecutive nodes,
+ * or 3-D tiles, per lbm_batch_set_schedule); lbm_batch_step replays a
  * captured hipGraph of graph_steps such launches when it can.  The update
  * of each node is the same as lbm_step's (a simulation gives bitwise the
  * same state batched or alone).
