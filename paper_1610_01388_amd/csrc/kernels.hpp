@@ -106,8 +106,9 @@ struct NodeArgs {
 };
 
 // Batched sweep: many independent all-fluid domains (walls only through
-// non-periodic axes) stepped together.  Each simulation is cut into tiles of
-// 256 nodes; one work item = one tile; a persistent grid walks the work list.
+// non-periodic axes) stepped together.  Each simulation is cut into work
+// items of 256 nodes (runs of consecutive nodes, or 3-D tiles); a persistent
+// grid walks the work list.
 struct BatchSim {
     int nx, ny, nz;
     int per[3];

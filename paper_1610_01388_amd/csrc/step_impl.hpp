@@ -242,10 +242,11 @@ __global__ __launch_bounds__(256) void k_step_compact(const StepArgs a, const ui
     using T = typename Store<PREC>::T;
     // SEL: neighbour addresses by selecting a 32-bit slot and one of two
     // wave-uniform array bases (no branch, fewer registers: more waves per
-    // SIMD for the FP64 operators with a per-node solve or a tau field);
-    // otherwise one 64-bit index per direction, which the compiler turns
-    // into branches but which measured faster for IR and reduced precision.
-    constexpr bool SEL = PREC == PREC_F64 && op_base(OP) != OP_IR;
+    // SIMD for the FP64 operators with a per-node solve or a tau field, and
+    // for the reduced-precision kernels that hold the FP64 redo); otherwise
+    // one 64-bit index per direction, which the compiler turns into branches
+    // but which measured faster for FP64 IR and plain reduced precision.
+    constexpr bool SEL = (PREC == PREC_F64 && op_base(OP) != OP_IR) || (OP & OP_FB) != 0;
 
     const int b = blockIdx.x;
     const int tile = (b & 7) * a.tiles_per_xcd + (b >> 3);
@@ -591,6 +592,7 @@ __global__ __launch_bounds__(256) void k_pull_slots(const StepArgs a)
         for (int i = 0; i < Q; ++i) {
             const int r = (1 - L::cy[i]) + 3 * (1 - L::cz[i]);  // row of x - c_i
             const bool fl = (nbf >> (3 * r + 1 - L::cx[i])) & 1;
+            // branch-free: the 32-bit slot and one of two wave-uniform array bases
             const int dn = PAT == PAT_AB ? i : opp(i), db = PAT == PAT_AB ? opp(i) : i;
             const uint32_t sl = fl ? nbi(-L::cx[i], r) : (uint32_t)k;
             h[i] = decode<PREC>((fl ? A + dn * St : A + db * St)[sl], L::w[i], a.h16_scale);
