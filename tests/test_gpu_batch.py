@@ -190,3 +190,68 @@ def test_duct_sweep_recipe_runs_fp32():
                        precision="FP32", layout="DENSE")
         d.step(50)
         assert np.array_equal(b.read_populations(k)[0], d.read_populations()[0])
+
+
+OTHER_LATTICES = {
+    "D2Q9": [dict(lattice="D2Q9", dims=(33, 37, 1), periodic=(0, 0, 1), op="IR", nu_p=0.1, sigma_y=2e-4, m=0.0,
+                  g=(3e-5, 0.0, 0.0)),
+             dict(lattice="D2Q9", dims=(70, 5, 1), periodic=(1, 0, 1), op="PR", nu_p=0.05, sigma_y=1e-4, m=1e4,
+                  g=(2e-5, 0.0, 0.0)),
+             dict(lattice="D2Q9", dims=(9, 300, 1), periodic=(1, 1, 1), op="IR", nu_p=0.2, sigma_y=0.0, m=0.0,
+                  g=(1e-5, 1e-5, 0.0))],
+    "D3Q27": [dict(lattice="D3Q27", dims=(33, 17, 4), periodic=(0, 0, 1), op="IR", nu_p=0.1, sigma_y=2e-4, m=0.0,
+                   g=(0.0, 0.0, 3e-5)),
+              dict(lattice="D3Q27", dims=(9, 9, 9), periodic=(1, 1, 1), op="PR", nu_p=0.05, sigma_y=1e-4, m=1e4,
+                   g=(2e-5, 1e-5, 0.0)),
+              dict(lattice="D3Q27", dims=(70, 5, 3), periodic=(1, 0, 0), op="PR", nu_p=0.1, sigma_y=3e-4, m=1e3,
+                   g=(2e-5, 0.0, 0.0))],
+}
+
+
+@pytest.mark.parametrize("name,lat", [("D2Q9", 0), ("D3Q27", 2)])
+def test_other_lattices_every_schedule(name, lat):
+    """D2Q9 and D3Q27 batches: under every tile policy (incl. runs of
+    consecutive nodes, the default) and both work-item orders each
+    simulation ends bitwise equal to its single-domain run, and the default
+    schedule matches the oracle (FP64 bar)."""
+    from paper_1610_01388_amd import lbm
+    cases = OTHER_LATTICES[name]
+    perm = perm_lib_from_oracle(lat)
+    states = []
+    for k, c in enumerate(cases):
+        P, tau = random_state(lat, int(np.prod(c["dims"])), 70 + k, amp=1e-2, nu_p=c["nu_p"])
+        states.append((P, tau, perm))
+    steps = 9
+    ref = []
+    for k, c in enumerate(cases):
+        P, tau, _ = states[k]
+        d = lbm.Domain(c["lattice"], c["dims"], c["periodic"], c["op"], c["nu_p"], c["sigma_y"], m=c["m"], g=c["g"],
+                       layout="DENSE")
+        d.write_populations(P[perm], tau if c["op"] == "PR" else None)
+        d.step(steps)
+        ref.append(d.read_populations()[0])
+        d.close()
+    for pol in (0, 1, 2, 3):
+        for order in (0, 1):
+            b = _make_batch(cases, states, graph_steps=4)
+            b.set_schedule(pol, order)
+            b.step(steps)
+            for k in range(len(cases)):
+                assert np.array_equal(b.read_populations(k)[0], ref[k]), (name, pol, order, k)
+            b.close()
+    b = _make_batch(cases, states, graph_steps=4)
+    assert b.schedule() == (3, 0)
+    b.step(steps)
+    for k, c in enumerate(cases):
+        P, tau, _ = states[k]
+        rh = oracle.rheology(oracle.PR if c["op"] == "PR" else oracle.IR, c["nu_p"], c["sigma_y"], c["m"], 1e-8,
+                             0.25, c["g"])
+        od = oracle.Domain(lat, c["dims"], c["periodic"], rh)
+        od.set_state(P, tau)
+        od.step(steps)
+        rho_o, u_o, _, uy_o = od.moments()
+        rho_b, u_b, _, uy_b = b.moments(k)
+        assert l2rel(u_b, u_o) <= 1e-10
+        assert np.max(np.abs(rho_b - rho_o)) <= 1e-12
+        assert np.array_equal(uy_b, uy_o)
+    b.close()
