@@ -37,6 +37,26 @@ def test_reduced_precision_vs_oracle(lat, op, precision):
     assert np.max(np.abs(got[0] - ref[0])[fluid]) <= PREC_TOL[precision]["rho"]
 
 
+@pytest.mark.parametrize("form", [("AA", "ROWS"), ("AA", "SLOTS"), ("AB", "ROWS")])
+@pytest.mark.parametrize("op", ["IR", "PR"])
+@pytest.mark.parametrize("lat", [0, 1, 2])
+def test_fp32_with_fallback_vs_oracle(lat, op, form):
+    """FP32 storage with the FP64 redo compiled in (kernels of their own):
+    every lattice, both operators, both compact neighbour kernels and A/B,
+    against the FP64 oracle at the FP32 bars."""
+    scheme, pull = form
+    dims = {0: (70, 37, 1), 1: (70, 13, 9), 2: (37, 11, 13)}[lat]
+    per = (1, 0, 1)
+    N = int(np.prod(dims))
+    mask = random_mask(N, 310 + lat, 0.15)
+    kw = {"layout": "COMPACT", "fp64_fallback": True, "fallback_band": 0.5 if op == "IR" else 1.0}
+    ref, got, _, _ = run_pair(lat, dims, per, op, 40, mask=mask, seed=13, gpu_kw=kw, precision="FP32", scheme=scheme,
+                              pull_form=pull)
+    fluid = mask == 0
+    assert l2rel(got[1], ref[1]) <= PREC_TOL["FP32"]["u"]
+    assert np.max(np.abs(got[0] - ref[0])[fluid]) <= PREC_TOL["FP32"]["rho"]
+
+
 @pytest.mark.parametrize("precision", ["FP32", "FP16"])
 def test_fp64_fallback_counts_and_matches(precision):
     """The FP64 redo of near-yield nodes is exercised (counted by the fused
