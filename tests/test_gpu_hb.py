@@ -14,7 +14,8 @@ from support import l2rel, random_mask, run_pair
 pytestmark = pytest.mark.gpu
 
 CASES = [(0, (70, 37, 1), (1, 0, 1)), (1, (70, 13, 9), (1, 0, 1)), (2, (37, 11, 13), (0, 1, 1))]
-FORMS = [("AA", {"layout": "COMPACT"}, "ROWS"), ("AA", {"layout": "COMPACT"}, "SLOTS"), ("AB", {"layout": "DENSE"}, None)]
+FORMS = [("AA", {"layout": "COMPACT"}, "ROWS"), ("AA", {"layout": "COMPACT"}, "SLOTS"), ("AB", {"layout": "DENSE"}, None),
+         ("AB", {"layout": "COMPACT"}, "ROWS")]
 
 
 @pytest.mark.parametrize("form", range(len(FORMS)))
