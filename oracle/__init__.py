@@ -29,7 +29,7 @@ def build(force: bool = True) -> str:
     """Compile the oracle with gcc (-O2, no fast-math)."""
     if force or not os.path.exists(LIB):
         tmp = LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-Wall",
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-Wall", "-fopenmp",
                                "-fno-fast-math", "-ffp-contract=off", SRC, "-o", tmp, "-lm"])
         os.replace(tmp, LIB)
     return LIB
@@ -97,6 +97,8 @@ def lib():
         L.orc_set_state.argtypes = [ctypes.c_void_p, dp, dp]
         L.orc_get_state.argtypes = [ctypes.c_void_p, dp, dp]
         L.orc_step.argtypes = [ctypes.c_void_p, ctypes.c_int64]
+        L.orc_set_threads.argtypes = [ctypes.c_int]
+        L.orc_set_threads.restype = ctypes.c_int
         L.orc_time.argtypes = [ctypes.c_void_p]
         L.orc_time.restype = ctypes.c_int64
         L.orc_moments.argtypes = [ctypes.c_void_p, dp, dp, dp, ctypes.POINTER(ctypes.c_uint8)]
@@ -104,6 +106,12 @@ def lib():
         L.orc_residual.argtypes = [ctypes.c_void_p, dp, ctypes.c_int, dp]
         _lib = L
     return _lib
+
+
+def set_threads(n: int = 0) -> int:
+    """Threads the oracle's steps use (n > 0 sets the count); returns the
+    count in effect.  Results are identical for every count."""
+    return lib().orc_set_threads(int(n))
 
 
 def _dp(a):

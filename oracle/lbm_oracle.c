@@ -19,6 +19,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define CS2 (1.0 / 3.0) /* lattice speed of sound squared, Sec. 2 */
 #define QMAX 27
@@ -705,54 +708,79 @@ static void collide_node(const orc_domain* dom, const double* fbar, double tau_p
     }
 }
 
+/* Nodes are updated independently (each reads the previous state and writes
+ * only its own entries), so the rows (y, z) may be shared among threads: the
+ * arithmetic of every node, and hence the result, is the same for any thread
+ * count. */
 void orc_step(orc_domain* dom, int64_t nsteps)
 {
-    double fbar[QMAX], fpost[QMAX], u[3], nu;
-    int uy;
+    const int64_t rows = (int64_t)dom->n[1] * dom->n[2];
     for (int64_t s = 0; s < nsteps; ++s) {
-        for (int z = 0; z < dom->n[2]; ++z)
-            for (int y = 0; y < dom->n[1]; ++y)
-                for (int x = 0; x < dom->n[0]; ++x) {
-                    int64_t n = x + (int64_t)dom->n[0] * (y + (int64_t)dom->n[1] * z);
-                    if (dom->solid[n]) {
-                        for (int i = 0; i < dom->L.q; ++i) dom->Pnew[i * dom->N + n] = 0.0;
-                        dom->taunew[n] = dom->tau[n];
-                        continue;
-                    }
-                    pull(dom, x, y, z, fbar);
-                    collide_node(dom, fbar, dom->tau[n], fpost, &dom->taunew[n], u, &nu, &uy);
-                    for (int i = 0; i < dom->L.q; ++i) dom->Pnew[i * dom->N + n] = fpost[i];
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static)
+#endif
+        for (int64_t r = 0; r < rows; ++r) {
+            const int y = (int)(r % dom->n[1]), z = (int)(r / dom->n[1]);
+            double fbar[QMAX], fpost[QMAX], u[3], nu;
+            int uy;
+            for (int x = 0; x < dom->n[0]; ++x) {
+                int64_t n = x + (int64_t)dom->n[0] * (y + (int64_t)dom->n[1] * z);
+                if (dom->solid[n]) {
+                    for (int i = 0; i < dom->L.q; ++i) dom->Pnew[i * dom->N + n] = 0.0;
+                    dom->taunew[n] = dom->tau[n];
+                    continue;
                 }
+                pull(dom, x, y, z, fbar);
+                collide_node(dom, fbar, dom->tau[n], fpost, &dom->taunew[n], u, &nu, &uy);
+                for (int i = 0; i < dom->L.q; ++i) dom->Pnew[i * dom->N + n] = fpost[i];
+            }
+        }
         double* tp = dom->P; dom->P = dom->Pnew; dom->Pnew = tp;
         double* tt = dom->tau; dom->tau = dom->taunew; dom->taunew = tt;
         dom->t++;
     }
 }
 
+int orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
+}
+
 void orc_moments(const orc_domain* dom, double* rho, double* u, double* nu_app,
                  uint8_t* unyielded)
 {
-    double fbar[QMAX], fpost[QMAX], uo[3], nu, tau_new, r, j[3];
-    int uy;
-    for (int z = 0; z < dom->n[2]; ++z)
-        for (int y = 0; y < dom->n[1]; ++y)
-            for (int x = 0; x < dom->n[0]; ++x) {
-                int64_t n = x + (int64_t)dom->n[0] * (y + (int64_t)dom->n[1] * z);
-                if (dom->solid[n]) {
-                    if (rho) rho[n] = 0.0;
-                    if (u) for (int a = 0; a < 3; ++a) u[a * dom->N + n] = 0.0;
-                    if (nu_app) nu_app[n] = 0.0;
-                    if (unyielded) unyielded[n] = 0;
-                    continue;
-                }
-                pull(dom, x, y, z, fbar);
-                density_momentum(&dom->L, fbar, &r, j);
-                collide_node(dom, fbar, dom->tau[n], fpost, &tau_new, uo, &nu, &uy);
-                if (rho) rho[n] = r;
-                if (u) for (int a = 0; a < 3; ++a) u[a * dom->N + n] = uo[a];
-                if (nu_app) nu_app[n] = nu;
-                if (unyielded) unyielded[n] = (uint8_t)uy;
+    const int64_t rows = (int64_t)dom->n[1] * dom->n[2];
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static)
+#endif
+    for (int64_t row = 0; row < rows; ++row) {
+        const int y = (int)(row % dom->n[1]), z = (int)(row / dom->n[1]);
+        double fbar[QMAX], fpost[QMAX], uo[3], nu, tau_new, r, j[3];
+        int uy;
+        for (int x = 0; x < dom->n[0]; ++x) {
+            int64_t n = x + (int64_t)dom->n[0] * (y + (int64_t)dom->n[1] * z);
+            if (dom->solid[n]) {
+                if (rho) rho[n] = 0.0;
+                if (u) for (int a = 0; a < 3; ++a) u[a * dom->N + n] = 0.0;
+                if (nu_app) nu_app[n] = 0.0;
+                if (unyielded) unyielded[n] = 0;
+                continue;
             }
+            pull(dom, x, y, z, fbar);
+            density_momentum(&dom->L, fbar, &r, j);
+            collide_node(dom, fbar, dom->tau[n], fpost, &tau_new, uo, &nu, &uy);
+            if (rho) rho[n] = r;
+            if (u) for (int a = 0; a < 3; ++a) u[a * dom->N + n] = uo[a];
+            if (nu_app) nu_app[n] = nu;
+            if (unyielded) unyielded[n] = (uint8_t)uy;
+        }
+    }
 }
 
 void orc_monitors(const orc_domain* dom, double* out, int64_t* counts)

@@ -98,6 +98,10 @@ void orc_set_state(orc_domain* dom, const double* P, const double* tau);
 void orc_get_state(const orc_domain* dom, double* P, double* tau);
 /* nsteps full updates: pull-stream with bounce-back, then collide. */
 void orc_step(orc_domain* dom, int64_t nsteps);
+/* Threads that orc_step and orc_moments share the rows among (n > 0 sets
+ * it; built without OpenMP: always 1).  Returns the count in effect.  The
+ * results do not depend on it. */
+int orc_set_threads(int n);
 int64_t orc_time(const orc_domain* dom);
 /* Moments at the current time.  rho[N], u[3*N] (component-major u[a*N+n]),
  * nu_app[N] (PR only; may be NULL), unyielded[N] (may be NULL).  Solid nodes

@@ -1,5 +1,7 @@
 """Plant plausible mistakes in a copy of the oracle (on the CPU) and check
-that the pins catch each one.  Several mutations are the literal forms of
+that the pins catch each one (among them: streaming that ignores interior
+solids, and a superficial flux divided by the fluid nodes instead of all
+nodes, both caught by the brute-force comparison on tiny grids).  Several mutations are the literal forms of
 passages that are garbled in the paper (the 3/2 prefactor of f_sigma, the
 coefficient 4 of the IR force term, the yield test T >= sigma_y, the
 deviator sigma - Tr(sigma) I, the interpolation denominator of Eq. 37); the
@@ -53,17 +55,21 @@ MUTATIONS = {
     "hb_stress_from_full_s": ("sig_mag = Tn - 0.5 * s_mag;", "sig_mag = Tn - s_mag;"),
     "hb_bracket_too_small": ("double lo = 0.0, hi = 2.0 * (Tn - sqrt(2.0) * rh->sigma_y);",
                              "double lo = 0.0, hi = (Tn - sqrt(2.0) * rh->sigma_y);"),
+    "streaming_ignores_solids": ("    return dom->solid[m] ? -1 : m;", "    return m;"),
+    "flux_over_fluid_nodes": ("for (int a = 0; a < 3; ++a) out[a] = flux[a] / (double)dom->N;",
+                              "for (int a = 0; a < 3; ++a) out[a] = flux[a] / (double)nfl;"),
     "flow_axis_pri_ignored": ("(2.0 * rho * CS2);\n    if (rh->flow_axis >= 1 && rh->flow_axis <= 3) D[rh->flow_axis - 1]",
                               "(2.0 * rho * CS2);\n    if (0) D[rh->flow_axis - 1]"),
 }
 
-PIN_TESTS = ["tests/test_oracle_lattice.py", "tests/test_oracle_operators.py",
+PIN_TESTS = ["tests/test_oracle_lattice.py", "tests/test_oracle_bruteforce.py", "tests/test_oracle_operators.py",
              "tests/test_oracle_flows.py", "tests/test_oracle_residual.py", "tests/test_oracle_burnett.py",
              "tests/test_oracle_mrt.py", "tests/test_oracle_pri.py", "tests/test_oracle_hb.py"]
 # The pin file aimed at a mutation's area runs first (all files still run
 # until one fails), so that the suite does not spend minutes on flow pins
 # before reaching the one that targets the mistake.
-FIRST = {"residual_": "tests/test_oracle_residual.py", "flow_axis_": "tests/test_oracle_burnett.py",
+FIRST = {"streaming_": "tests/test_oracle_bruteforce.py", "flux_": "tests/test_oracle_bruteforce.py",
+         "residual_": "tests/test_oracle_residual.py", "flow_axis_": "tests/test_oracle_burnett.py",
          "pri_": "tests/test_oracle_pri.py", "mrt_": "tests/test_oracle_mrt.py", "hb_": "tests/test_oracle_hb.py"}
 
 
