@@ -113,8 +113,11 @@ typedef struct {
     double gamma_c;          /* PR: strain-rate cut-off (> 0), e.g. 1e-8      */
     double lambda_trt;       /* PR: TRT magic number (> 0), e.g. 0.25         */
     double g[3];             /* body force per unit mass                      */
-    double fallback_band;    /* IR: |T/(sqrt2 sigma_y) - 1| < band; PR:
-                                m*gamma_dot < band -> node done in FP64      */
+    double fallback_band;    /* FP64 redo (fp64_fallback) of the nodes whose
+                                stress lies within this relative band around
+                                the yield stress: IR |T/(sqrt2 sigma_y) - 1|
+                                < band, PR and PRI |rho nu_app gamma_dot /
+                                sigma_y - 1| < band (sigma_y > 0)          */
     int32_t fp16_scale_log2; /* FP16: k in h*2^k/w (0..24), e.g. 14           */
     int32_t flow_axis;       /* 0: off.  1, 2, 3: the flow is known to run along
                                 x, y, z; the collision then drops that axis's
@@ -233,14 +236,34 @@ int lbm_set_umax_limit(lbm_domain* dom, double umax);
 int lbm_read_moments(lbm_domain* dom, double* rho, double* u, double* nu_app,
                      uint8_t* unyielded);
 
-/* Checkpoint: the blob holds a header (descriptor, rheology, time, scheme
- * phase), the raw population storage, the PR field, the mask and the
- * residual monitor's reference velocity.  With
- * blob == NULL, lbm_save only reports the size in *bytes.  lbm_load rejects
- * (LBM_EFORMAT) a blob that is truncated or was saved from a domain with a
- * different descriptor.  Both synchronise. */
+/* Checkpoint.  The blob is a header followed by the payload:
+ *   header: magic "LBMCKPT1", format version 3, header size, the domain's
+ *     lbm_desc and lbm_rheology, the time (collisions done), the population
+ *     stride, the fluid count, the AA phase (0: post-collision state, 1:
+ *     streamed state; always 0 for A/B), q, the four payload part sizes and a
+ *     checksum of the payload (FNV-1a over 64-bit words in four interleaved
+ *     lanes);
+ *   payload: the raw population storage (q x stride elements of the storage
+ *     precision), the PR relaxation-time field (stride elements; absent for
+ *     the other operators), the mask (dense layout: N bytes, 1 = solid;
+ *     compact layout: the fluid bitmap, ny nz rows of ceil(nx / 64) 64-bit
+ *     words, bit b of word w set when node x = 64 w + b is fluid) and the
+ *     residual monitor's reference velocity (3 x stride doubles).
+ * With blob == NULL, lbm_save only reports the size in *bytes.  lbm_load
+ * validates the whole blob on the host before any device work and rejects
+ * it (LBM_EFORMAT) when it is truncated, saved from another descriptor, fails
+ * its checksum, or is inconsistent: a negative time, an AA phase outside
+ * {0, 1}, a mask byte other than 0 / 1, a fluid bit past a row's end, a fluid
+ * count or stride that the mask does not give.  The slot tables of the
+ * compact layout are rebuilt from the mask, never read from the blob.  The
+ * rheology in the blob is informational: the domain keeps its own (a state
+ * may be continued under other rheological parameters).  Both synchronise. */
 int lbm_save(lbm_domain* dom, void* blob, size_t* bytes);
 int lbm_load(lbm_domain* dom, const void* blob, size_t bytes);
+/* The validation lbm_load performs, for a domain of this descriptor and
+ * rheology, on the host alone (no device, no domain needed): LBM_OK or
+ * LBM_EFORMAT (LBM_EINVAL for an invalid descriptor or rheology). */
+int lbm_check_checkpoint(const lbm_desc* desc, const lbm_rheology* rh, const void* blob, size_t bytes);
 
 /* Tile shape of the step kernel: one node per thread, tx*ty*tz threads per
  * block, which must be 64, 128, 192 or 256; tz must be 1 for D2Q9; the

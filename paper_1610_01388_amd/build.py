@@ -1,8 +1,8 @@
 """Build the HIP library liblbm.so for gfx950 (in-tree, next to this file).
 
-Every .hip source under csrc/ is compiled to an object in parallel, then the
-objects are linked into one shared library exporting the C ABI of
-include/lbm.h.  Packed FP32 instructions are disabled (-packed-fp32-ops).
+Every .hip source under csrc/ (and the plain C++ host code, .cpp) is
+compiled to an object in parallel, then the objects are linked into one
+shared library exporting the C ABI of include/lbm.h.  Packed FP32 instructions are disabled (-packed-fp32-ops).
 """
 from __future__ import annotations
 
@@ -31,7 +31,11 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
+    if src.endswith(".cpp"):  # host code only: no device pass
+        cmd = [HIPCC, "-O2", "-std=c++17", "-fPIC", "-Wall", "-I", CSRC, "-I", os.path.join(ROOT, "include"),
+               "-c", src, "-o", obj]
+    else:
+        cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
@@ -40,7 +44,7 @@ def _compile(src: str) -> str:
 
 def build(jobs: int | None = None) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
+    srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip"))) + sorted(glob.glob(os.path.join(CSRC, "*.cpp")))
     jobs = jobs or min(len(srcs), os.cpu_count() or 4, 16)
     with cf.ThreadPoolExecutor(jobs) as ex:
         objs = list(ex.map(_compile, srcs))

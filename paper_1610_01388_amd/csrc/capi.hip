@@ -14,6 +14,7 @@
 #include <string>
 #include <vector>
 
+#include "host.hpp"
 #include "kernels.hpp"
 #include "lbm.h"
 
@@ -63,76 +64,30 @@ static_assert((int)OP_PR == (int)LBM_PR && (int)OP_IR == (int)LBM_IR && (int)OP_
                   (int)OP_IRHB == (int)LBM_IRHB,
               "kernel operator codes must equal the C ABI's lbm_operator values");
 
-int lattice_q(int lat) { return lat == 0 ? 9 : lat == 1 ? 19 : lat == 2 ? 27 : -1; }
-int lattice_d(int lat) { return lat == 0 ? 2 : 3; }
-size_t prec_bytes(int p) { return p == LBM_FP64 ? 8 : p == LBM_FP32 ? 4 : 2; }
-
-// Stride (in elements) between the direction arrays of the compact layout.
-// When the arrays lie a multiple of a large power of two apart in bytes, the
-// Q streams of one node -- and, in a box with no solids, the streams of
-// neighbouring planes too -- fall on the same HBM channels (an all-fluid
-// 256^3 D3Q27 FP64 box loses 16% of its bandwidth to it).  The stride is
-// rounded up to a multiple of 64 elements and then, unless its byte size
-// modulo 64 KiB is already within the middle half, padded until it is
-// 16 KiB.  The padding is below 64 KiB per array (kStridePad elements of
-// slack in every population buffer).
+// Population arrays carry kStridePad elements of slack beyond the node count
+// rounded to 64, room for compact_stride's padding (below 64 KiB per array).
 constexpr int64_t kStridePad = 32768;
-int64_t compact_stride(int64_t nf, int prec)
-{
-    const int64_t S = std::max<int64_t>(64, (nf + 63) / 64 * 64);
-    const int64_t P = 65536 / (int64_t)prec_bytes(prec);  // 64 KiB in elements
-    const int64_t r = S % P;
-    if (r >= P / 4 && r < 3 * P / 4) return S;
-    return S + ((P / 4 - r) % P + P) % P;
-}
 
 struct Layout {
     size_t pdf_copy, pdf, tau, mask, part, hist, rec, uprev, stage, work;
-    size_t bits_off, base_off, wstart_off, mask_compact;  // compact mask: bitmap, word bases, group words
+    size_t bits_off, base_off, wstart_off, recs_off, mask_compact;  // compact mask: bitmap, word bases, group
+                                                                    // words, segment records
     int64_t max_parts, npad;
     int W;
 };
 
 int check_desc(const lbm_desc* d)
 {
-    if (!d) return fail(LBM_EINVAL, "descriptor is NULL");
-    if (lattice_q(d->lattice) < 0) return fail(LBM_EINVAL, "unknown lattice %d", d->lattice);
-    if (d->nx < 1 || d->ny < 1 || d->nz < 1) return fail(LBM_EINVAL, "non-positive size %dx%dx%d", d->nx, d->ny, d->nz);
-    if (d->lattice == LBM_D2Q9 && d->nz != 1) return fail(LBM_EINVAL, "D2Q9 needs nz == 1");
-    if ((int64_t)d->nx * d->ny * d->nz > (int64_t)1 << 36) return fail(LBM_EINVAL, "domain too large");
-    if (d->precision < LBM_FP64 || d->precision > LBM_FP16) return fail(LBM_EINVAL, "unknown precision %d", d->precision);
-    if (d->scheme != LBM_AB && d->scheme != LBM_AA) return fail(LBM_EINVAL, "unknown scheme %d", d->scheme);
-    if (d->layout != LBM_COMPACT && d->layout != LBM_DENSE) return fail(LBM_EINVAL, "unknown layout %d", d->layout);
-    return LBM_OK;
+    std::string err;
+    const int rc = validate_desc(d, err);
+    return rc ? fail(rc, "%s", err.c_str()) : LBM_OK;
 }
 
 int check_rheology(const lbm_rheology* r)
 {
-    if (!r) return fail(LBM_EINVAL, "rheology is NULL");
-    if (r->op != LBM_PR && r->op != LBM_IR && r->op != LBM_PRI && r->op != LBM_IRHB)
-        return fail(LBM_EINVAL, "unknown operator %d", r->op);
-    if (r->op == LBM_IRHB && !(r->hb_n >= 0.2 && r->hb_n <= 5.0))
-        return fail(LBM_EINVAL, "hb_n (flow index) must lie in [0.2, 5]");
-    if (!(r->nu_p > 0)) return fail(LBM_EINVAL, "nu_p must be > 0 (tau > 1/2)");
-    if (!(r->sigma_y >= 0)) return fail(LBM_EINVAL, "sigma_y must be >= 0");
-    if (!(r->rho0 > 0)) return fail(LBM_EINVAL, "rho0 must be > 0");
-    for (int a = 0; a < 3; ++a)
-        if (!std::isfinite(r->g[a])) return fail(LBM_EINVAL, "body force must be finite");
-    if (r->op == LBM_PR || r->op == LBM_PRI) {
-        if (!(r->m >= 0)) return fail(LBM_EINVAL, "m must be >= 0");
-        if (!(r->gamma_c > 0)) return fail(LBM_EINVAL, "gamma_c must be > 0");
-        if (!(r->lambda_trt > 0)) return fail(LBM_EINVAL, "lambda_trt must be > 0");
-    }
-    if (r->fp16_scale_log2 < 0 || r->fp16_scale_log2 > 24) return fail(LBM_EINVAL, "fp16_scale_log2 outside 0..24");
-    if (!(r->fallback_band >= 0)) return fail(LBM_EINVAL, "fallback_band must be >= 0");
-    if (r->flow_axis < 0 || r->flow_axis > 3) return fail(LBM_EINVAL, "flow_axis must be 0 (off) or 1..3");
-    if (!(r->mrt_bulk >= 0 && r->mrt_bulk < 2) || !(r->mrt_even >= 0 && r->mrt_even < 2))
-        return fail(LBM_EINVAL, "MRT rates must lie in [0, 2) (0: the shear rate)");
-    if ((r->mrt_bulk > 0 || r->mrt_even > 0) && (r->op == LBM_IR || r->op == LBM_IRHB))
-        return fail(LBM_EINVAL, "the MRT base collision applies to the PR operators");
-    if (r->mrt_bulk > 0 && r->op == LBM_PRI)
-        return fail(LBM_EINVAL, "PRI takes no separate MRT bulk rate (its tau solve scales the whole strain rate)");
-    return LBM_OK;
+    std::string err;
+    const int rc = validate_rheology(r, err);
+    return rc ? fail(rc, "%s", err.c_str()) : LBM_OK;
 }
 
 Layout layout_of(const lbm_desc* d, const lbm_rheology* r)
@@ -149,7 +104,8 @@ Layout layout_of(const lbm_desc* d, const lbm_rheology* r)
     L.bits_off = 0;
     L.base_off = align_up(words * 8);
     L.wstart_off = L.base_off + align_up(words * 4);
-    L.mask_compact = L.wstart_off + align_up(((size_t)N / 64 + 1) * 4);
+    L.recs_off = L.wstart_off + align_up(((size_t)N / 64 + 1) * 4);
+    L.mask_compact = L.recs_off + align_up((size_t)L.W * (d->ny + 2) * (d->nz + 2) * sizeof(SegRec));
     L.mask = std::max(align_up((size_t)N), L.mask_compact);
     L.max_parts = N / 32 + 64;
     L.part = 0;
@@ -344,6 +300,7 @@ StepArgs step_args(lbm_domain* dm)
     a.bits = (const uint64_t*)(dm->mask + dm->L.bits_off);
     a.wbase = (const uint32_t*)(dm->mask + dm->L.base_off);
     a.wstart = (const uint32_t*)(dm->mask + dm->L.wstart_off);
+    a.recs = (const SegRec*)(dm->mask + dm->L.recs_off);
     a.W = dm->L.W;
     a.S = dm->S;
     a.nfluid = dm->Nf;
@@ -368,8 +325,9 @@ StepArgs step_args(lbm_domain* dm)
     a.ntiles = a.ntx * a.nty * a.ntz;
     a.tiles_per_xcd = (a.ntiles + 7) / 8;
     tile_order(dm, a.ntx, a.nty, a.ntz, a.bry, a.brz);
-    // non-temporal hints only pay when the state does not fit the 256 MB
-    // last-level cache
+    // non-temporal hints when the population state exceeds 512 MiB, twice
+    // the 256 MB last-level cache: a state that still partly fits keeps its
+    // cache hits
     a.stream_hint = (double)dm->Q * (double)dm->S * (double)prec_bytes(dm->d.precision) > 512.0 * (1 << 20) ? 1 : 0;
     a.fallback = (dm->d.precision != LBM_FP64 && dm->r.fp64_fallback) ? 1 : 0;
     a.h16_scale = std::ldexp(1.0f, -dm->r.fp16_scale_log2);
@@ -446,9 +404,15 @@ int upload_mask(lbm_domain* dm, const uint8_t* host_mask)
 {
     if (dm->d.layout == LBM_DENSE) {
         if (host_mask) {
-            HIPCHK(hipMemcpyAsync(dm->mask, host_mask, (size_t)dm->N, hipMemcpyHostToDevice, dm->stream));
+            // stored as 0 / 1 bytes whatever nonzero value marks a solid
+            std::vector<uint8_t> m((size_t)dm->N);
             int64_t nf = 0;
-            for (int64_t n = 0; n < dm->N; ++n) nf += host_mask[n] == 0;
+            for (int64_t n = 0; n < dm->N; ++n) {
+                m[(size_t)n] = host_mask[n] ? 1 : 0;
+                nf += host_mask[n] == 0;
+            }
+            HIPCHK(hipMemcpyAsync(dm->mask, m.data(), (size_t)dm->N, hipMemcpyHostToDevice, dm->stream));
+            HIPCHK(hipStreamSynchronize(dm->stream));
             dm->Nf = nf;
         } else {
             HIPCHK(launch_fill_u8(dm->mask, dm->N, 0, dm->stream));
@@ -458,34 +422,23 @@ int upload_mask(lbm_domain* dm, const uint8_t* host_mask)
         HIPCHK(hipStreamSynchronize(dm->stream));
         return LBM_OK;
     }
-    const int nx = dm->d.nx, W = dm->L.W;
-    const int64_t rows = (int64_t)dm->d.ny * dm->d.nz;
-    std::vector<uint64_t> bits((size_t)rows * W, 0);
-    std::vector<uint32_t> base((size_t)rows * W, 0);
-    std::vector<uint32_t> wstart;  // word holding slot 64 g
-    wstart.reserve((size_t)(dm->N / 64 + 1));
-    uint64_t count = 0;
-    for (int64_t r = 0; r < rows; ++r) {
-        for (int w = 0; w < W; ++w) {
-            uint64_t word = 0;
-            for (int b = 0; b < 64; ++b) {
-                const int x = 64 * w + b;
-                if (x < nx && (!host_mask || host_mask[r * nx + x] == 0)) word |= 1ull << b;
-            }
-            bits[(size_t)r * W + w] = word;
-            base[(size_t)r * W + w] = (uint32_t)count;
-            count += (uint64_t)__builtin_popcountll(word);
-            if (count > 0xFFFFFFFFull) return fail(LBM_EINVAL, "compact layout holds at most 2^32-1 fluid nodes");
-            while ((uint64_t)wstart.size() * 64 < count) wstart.push_back((uint32_t)(r * W + w));
-        }
-    }
-    dm->Nf = (int64_t)count;
-    dm->S = compact_stride(dm->Nf, dm->d.precision);
-    HIPCHK(hipMemcpyAsync(dm->mask + dm->L.bits_off, bits.data(), bits.size() * 8, hipMemcpyHostToDevice, dm->stream));
-    HIPCHK(hipMemcpyAsync(dm->mask + dm->L.base_off, base.data(), base.size() * 4, hipMemcpyHostToDevice, dm->stream));
-    if (!wstart.empty())
-        HIPCHK(hipMemcpyAsync(dm->mask + dm->L.wstart_off, wstart.data(), wstart.size() * 4, hipMemcpyHostToDevice,
-                              dm->stream));
+    int per[3];
+    for (int k = 0; k < 3; ++k) per[k] = dm->d.periodic[k] ? 1 : 0;
+    if (dm->D == 2) per[2] = 1;
+    CompactMask cm;
+    std::string err;
+    if (!build_compact_mask(dm->d.nx, dm->d.ny, dm->d.nz, per, host_mask, cm, err)) return fail(LBM_EINVAL, "%s", err.c_str());
+    dm->Nf = cm.fluid;
+    dm->S = compact_stride(dm->Nf, prec_bytes(dm->d.precision));
+    HIPCHK(hipMemcpyAsync(dm->mask + dm->L.bits_off, cm.bits.data(), cm.bits.size() * 8, hipMemcpyHostToDevice,
+                          dm->stream));
+    HIPCHK(hipMemcpyAsync(dm->mask + dm->L.base_off, cm.base.data(), cm.base.size() * 4, hipMemcpyHostToDevice,
+                          dm->stream));
+    if (!cm.wstart.empty())
+        HIPCHK(hipMemcpyAsync(dm->mask + dm->L.wstart_off, cm.wstart.data(), cm.wstart.size() * 4,
+                              hipMemcpyHostToDevice, dm->stream));
+    HIPCHK(hipMemcpyAsync(dm->mask + dm->L.recs_off, cm.recs.data(), cm.recs.size() * sizeof(SegRec),
+                          hipMemcpyHostToDevice, dm->stream));
     HIPCHK(hipStreamSynchronize(dm->stream));
     return LBM_OK;
 }
@@ -745,29 +698,15 @@ int lbm_read_moments(lbm_domain* dm, double* rho, double* u, double* nu_app, uin
 }
 
 // ---------------------------------------------------------------------------
-// checkpoints
+// checkpoints (format and validation: host.hpp)
 // ---------------------------------------------------------------------------
-namespace {
-struct CkptHeader {
-    char magic[8];
-    uint32_t version, header_bytes;
-    lbm_desc desc;
-    lbm_rheology rh;
-    int64_t t, stride, fluid;
-    int32_t parity, q;
-    uint64_t pdf_bytes, tau_bytes, mask_bytes, uprev_bytes;
-};
-constexpr uint32_t kCkptVersion = 2;
-const char kMagic[8] = {'L', 'B', 'M', 'C', 'K', 'P', 'T', '1'};
-}  // namespace
-
 int lbm_save(lbm_domain* dm, void* blob, size_t* bytes)
 {
     int rc = need_bound(dm);
     if (rc) return rc;
     if (!bytes) return fail(LBM_EINVAL, "bytes is NULL");
     CkptHeader h{};
-    memcpy(h.magic, kMagic, 8);
+    memcpy(h.magic, kCkptMagic, 8);
     h.version = kCkptVersion;
     h.header_bytes = sizeof(CkptHeader);
     h.desc = dm->d;
@@ -777,30 +716,43 @@ int lbm_save(lbm_domain* dm, void* blob, size_t* bytes)
     h.fluid = dm->Nf;
     h.parity = dm->parity;
     h.q = dm->Q;
-    h.pdf_bytes = (uint64_t)dm->Q * dm->S * prec_bytes(dm->d.precision);
-    h.tau_bytes = dm->tau ? (uint64_t)dm->S * (dm->d.precision == LBM_FP64 ? 8 : 4) : 0;
-    h.mask_bytes = dm->d.layout == LBM_DENSE ? (uint64_t)dm->N : (uint64_t)dm->L.mask_compact;
-    h.uprev_bytes = (uint64_t)3 * dm->S * sizeof(double);
+    checkpoint_sizes(dm->d, dm->r.op == LBM_PR, dm->S, h);
     const size_t need = sizeof(h) + h.pdf_bytes + h.tau_bytes + h.mask_bytes + h.uprev_bytes;
     if (!blob) {
         *bytes = need;
         return LBM_OK;
     }
     if (*bytes < need) return fail(LBM_EINVAL, "blob too small: %zu < %zu", *bytes, need);
-    char* p = (char*)blob;
+    char* const payload = (char*)blob + sizeof h;
+    char* p = payload;
     HIPCHK(hipStreamSynchronize(dm->stream));
-    memcpy(p, &h, sizeof h);
-    p += sizeof h;
     const char* src = dm->d.scheme == LBM_AB ? copy_ptr(dm, dm->cur) : dm->pdf;
     HIPCHK(hipMemcpy(p, src, h.pdf_bytes, hipMemcpyDeviceToHost));
     p += h.pdf_bytes;
     if (h.tau_bytes) HIPCHK(hipMemcpy(p, dm->tau, h.tau_bytes, hipMemcpyDeviceToHost));
     p += h.tau_bytes;
-    HIPCHK(hipMemcpy(p, dm->mask, h.mask_bytes, hipMemcpyDeviceToHost));
+    // the dense mask bytes, or the compact layout's fluid bitmap (everything
+    // else of the compact mask is rebuilt from it on load)
+    HIPCHK(hipMemcpy(p, dm->mask + (dm->d.layout == LBM_DENSE ? 0 : dm->L.bits_off), h.mask_bytes,
+                     hipMemcpyDeviceToHost));
     p += h.mask_bytes;
     // the residual monitor's reference velocity: components at 0, S, 2S
     HIPCHK(hipMemcpy(p, dm->work + dm->L.uprev, h.uprev_bytes, hipMemcpyDeviceToHost));
+    h.checksum = checkpoint_checksum(h, payload, need - sizeof h);
+    memcpy(blob, &h, sizeof h);
     *bytes = need;
+    return LBM_OK;
+}
+
+int lbm_check_checkpoint(const lbm_desc* desc, const lbm_rheology* rh, const void* blob, size_t bytes)
+{
+    int rc = check_desc(desc);
+    if (rc) return rc;
+    if ((rc = check_rheology(rh))) return rc;
+    if (!blob) return fail(LBM_EINVAL, "blob is NULL");
+    CkptView v;
+    std::string err;
+    if ((rc = parse_checkpoint(*desc, rh->op == LBM_PR, blob, bytes, v, err))) return fail(rc, "%s", err.c_str());
     return LBM_OK;
 }
 
@@ -809,36 +761,22 @@ int lbm_load(lbm_domain* dm, const void* blob, size_t bytes)
     int rc = need_bound(dm);
     if (rc) return rc;
     if (!blob) return fail(LBM_EINVAL, "blob is NULL");
-    CkptHeader h;
-    if (bytes < sizeof h) return fail(LBM_EFORMAT, "checkpoint truncated (header)");
-    memcpy(&h, blob, sizeof h);
-    if (memcmp(h.magic, kMagic, 8) != 0 || h.version != kCkptVersion || h.header_bytes != sizeof h)
-        return fail(LBM_EFORMAT, "not a checkpoint of this library version");
-    if (memcmp(&h.desc, &dm->d, sizeof(lbm_desc)) != 0 || h.q != dm->Q)
-        return fail(LBM_EFORMAT, "checkpoint was saved from a different domain descriptor");
-    const uint64_t mask_expect = dm->d.layout == LBM_DENSE ? (uint64_t)dm->N : (uint64_t)dm->L.mask_compact;
-    if (h.stride < 1 || h.stride > dm->L.npad || h.fluid < 0 || h.fluid > h.stride)
-        return fail(LBM_EFORMAT, "checkpoint stride does not fit the domain");
-    const uint64_t tau_expect = dm->tau ? (uint64_t)h.stride * (dm->d.precision == LBM_FP64 ? 8 : 4) : 0;
-    if (h.pdf_bytes != (uint64_t)dm->Q * h.stride * prec_bytes(dm->d.precision) || h.tau_bytes != tau_expect ||
-        h.mask_bytes != mask_expect || h.uprev_bytes != (uint64_t)3 * h.stride * sizeof(double))
-        return fail(LBM_EFORMAT, "checkpoint sizes do not match the domain");
-    if (bytes < sizeof h + h.pdf_bytes + h.tau_bytes + h.mask_bytes + h.uprev_bytes)
-        return fail(LBM_EFORMAT, "checkpoint truncated");
-    const char* p = (const char*)blob + sizeof h;
-    HIPCHK(hipStreamSynchronize(dm->stream));
+    CkptView v;
+    std::string err;
+    // everything is checked on the host before the device is touched
+    if ((rc = parse_checkpoint(dm->d, dm->r.op == LBM_PR, blob, bytes, v, err))) return fail(rc, "%s", err.c_str());
+    std::vector<uint8_t> mask;
+    checkpoint_mask(dm->d, v, mask);
+    // the slot tables are rebuilt from the mask, never taken from the blob
+    if ((rc = upload_mask(dm, mask.data()))) return rc;
+    if (dm->Nf != v.h.fluid || dm->S != v.h.stride)
+        return fail(LBM_EFORMAT, "checkpoint mask gives another fluid count or stride");
     dm->cur = 0;
-    HIPCHK(hipMemcpy(dm->pdf, p, h.pdf_bytes, hipMemcpyHostToDevice));
-    p += h.pdf_bytes;
-    if (h.tau_bytes) HIPCHK(hipMemcpy(dm->tau, p, h.tau_bytes, hipMemcpyHostToDevice));
-    p += h.tau_bytes;
-    HIPCHK(hipMemcpy(dm->mask, p, h.mask_bytes, hipMemcpyHostToDevice));
-    p += h.mask_bytes;
-    HIPCHK(hipMemcpy(dm->work + dm->L.uprev, p, h.uprev_bytes, hipMemcpyHostToDevice));
-    dm->t = h.t;
-    dm->S = h.stride;
-    dm->Nf = h.fluid;
-    dm->parity = h.parity;
+    HIPCHK(hipMemcpy(dm->pdf, v.pdf, v.h.pdf_bytes, hipMemcpyHostToDevice));
+    if (v.h.tau_bytes) HIPCHK(hipMemcpy(dm->tau, v.tau, v.h.tau_bytes, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(dm->work + dm->L.uprev, v.uprev, v.h.uprev_bytes, hipMemcpyHostToDevice));
+    dm->t = v.h.t;
+    dm->parity = v.h.parity;
     dm->hist_written = dm->hist_read = 0;
     return LBM_OK;
 }

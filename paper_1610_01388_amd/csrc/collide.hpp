@@ -282,8 +282,12 @@ __device__ __forceinline__ Pre<C> rheology(const Moments<C>& mo, const Coll<C>& 
         r.gamma = gamma;
         r.tau_p = C(0.5) + C(3) * nu;
         r.tau_m = C(0.5) + p.lambda / (r.tau_p - C(0.5));
-        r.unyielded = r.rho * nu * gamma < p.sigma_y;
-        r.near_yield = p.m * gamma < p.band;
+        // the regularised stress magnitude sqrt(sigma:sigma / 2) = rho nu gamma
+        // against the yield stress: unyielded below it, redone in FP64 (when
+        // enabled) within the band around it
+        const C stress = r.rho * nu * gamma;
+        r.unyielded = stress < p.sigma_y;
+        r.near_yield = p.sigma_y > C(0) && fabs(stress - p.sigma_y) < p.band * p.sigma_y;
         r.Tn = 0;
     } else {
 #pragma unroll

@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include "collide.hpp"
+#include "layout.hpp"
 
 namespace lbm {
 
@@ -45,6 +46,8 @@ __host__ __device__ constexpr bool mp_is_max(int k) { return k == MP_UMAX || k =
 //                  fluid node at or after x = 64*word, so k(x) = wbase +
 //                  popcount(bits below x).  wstart[g] names the word holding
 //                  slot 64 g (the slot kernels start their search there).
+//                  recs: the same rows as segment records with halo rows
+//                  (SegRec), read by the row-segment kernel.
 enum { LAYOUT_COMPACT = 0, LAYOUT_DENSE = 1 };  // same values as lbm_layout
 
 struct StepArgs {
@@ -55,6 +58,7 @@ struct StepArgs {
     const uint64_t* bits;  // compact: fluid bitmap [row][W]
     const uint32_t* wbase; // compact: [row][W]
     const uint32_t* wstart; // compact: per group of 64 slots, the word [row][W] holding its first slot
+    const SegRec* recs;    // compact: segment records [(ny + 2)(nz + 2)][W] (halo rows included)
     double* partials;      // MON: MP_COUNT doubles per tile (slot kernels: per block)
     double* uprev;         // MON: output velocity of the previous fused monitor, [3][S]; overwritten
     int64_t N;             // nodes

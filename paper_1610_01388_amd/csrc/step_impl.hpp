@@ -224,15 +224,17 @@ __global__ __launch_bounds__(256) void k_step(const StepArgs a)
 }
 
 // Compact-layout step: only fluid nodes have population slots.  A wavefront
-// is one 64-node segment of one row (y, z): block = 64 x ty x tz, one wave per
-// row segment.  For each of the 3 (2-D) or 9 (3-D) rows around it, the
-// segment's bitmap word and the words holding its left and right neighbours
-// are wave-uniform, so they are read once per wave; each lane then gets the
-// fluid flag and compact index of its x-1, x, x+1 neighbours in that row from
-// the word's rank below the lane (mbcnt) and single-bit tests.
+// is one 64-node segment of one row (y, z): block = tx x ty x tz with tx = 64,
+// 128 or 256, one wave per row segment.  For each of the 3 (2-D) or 9 (3-D)
+// rows around it, the segment's record (SegRec: bitmap word, slot base and
+// the slots of the segment's outer neighbours) is wave-uniform, one scalar
+// load per row; halo rows in the record table stand for the wrapped rows of
+// periodic axes and for the empty rows behind walls, so the nine loads carry
+// no branch and are all in flight together.  Each lane then gets the fluid
+// flag and slot of its x-1, x, x+1 neighbours in that row from the word's
+// rank below the lane (mbcnt) and single-bit tests.
 template <int LAT, int OP, int PREC, int PAT, bool MON>
-__global__ __launch_bounds__(256) void k_step_compact(const StepArgs a, const uint64_t* __restrict__ bits,
-                                                      const uint32_t* __restrict__ wbase)
+__global__ __launch_bounds__(256) void k_step_compact(const StepArgs a, const SegRec* __restrict__ recs)
 {
     using L = Lattice<LAT>;
     constexpr int Q = L::Q;
@@ -269,6 +271,9 @@ __global__ __launch_bounds__(256) void k_step_compact(const StepArgs a, const ui
     const int z = ttz * a.tz + lz;
     const bool wave_in = (y < a.ny) && (z < a.nz) && (x0 < a.nx);
     const int64_t St = a.S;
+    // a wave past the box edge reads the last row's records and keeps nothing
+    const int yc = min(y, a.ny - 1), zc = min(z, a.nz - 1), sc = min(seg, a.W - 1);
+    const uint64_t keep = wave_in ? ~0ull : 0ull;
 
     // Neighbourhood of node x: fluid flag of x + d (bit d of nbf, d = (dx, dy,
     // dz) in {-1,0,1}^3, index (dx+1) + 3 (dy+1) + 9 (dz+1)); for each of the
@@ -282,57 +287,40 @@ __global__ __launch_bounds__(256) void k_step_compact(const StepArgs a, const ui
 #pragma unroll
     for (int r = 0; r < 9; ++r) im[r] = li[r] = ri[r] = 0;
     const bool last = (lane == 63) || (x == a.nx - 1);
+    // the segment's last node: bits past it are zero, so the right-neighbour
+    // flag of that lane can be placed there in the shifted word
+    const int lastbit = min(63, a.nx - 1 - x0);
+    // all record loads first (straight-line, so they are in flight together)
+    uint64_t rb[9];
+    uint32_t rbase[9], rl[9], rr[9];
 #pragma unroll
-    for (int dz = -1; dz <= 1; ++dz) {
-        if (D == 2 && dz != 0) continue;
+    for (int r = 0; r < 9; ++r) {
+        rb[r] = 0;
+        rbase[r] = rl[r] = rr[r] = kNoSlot;
+        if (D == 2 && r / 3 != 1) continue;
+        const SegRec* rp = recs + rec_row(yc + r % 3 - 1, zc + r / 3 - 1, a.ny) * a.W + sc;
+        rb[r] = rp->bits;
+        rbase[r] = rp->base;
+        rl[r] = rp->lidx;
+        rr[r] = rp->ridx;
+    }
 #pragma unroll
-        for (int dy = -1; dy <= 1; ++dy) {
-            bool rv = wave_in;
-            int yy = y + dy, zz = z + dz;
-            if (yy < 0 || yy >= a.ny) {
-                if (a.per[1]) yy = (yy + a.ny) % a.ny;
-                else rv = false;
-            }
-            if (zz < 0 || zz >= a.nz) {
-                if (a.per[2]) zz = (zz + a.nz) % a.nz;
-                else rv = false;
-            }
-            uint64_t mb = 0;
-            uint32_t mbase = 0, lidx = 0, ridx = 0;
-            bool lf = false, rf = false;
-            if (rv) {
-                const int64_t row = ((int64_t)yy + (int64_t)a.ny * zz) * a.W;
-                mb = bits[row + seg];
-                mbase = wbase[row + seg];
-                int wl = -1, bl = 63;
-                if (x0 > 0) wl = seg - 1;
-                else if (a.per[0]) { wl = (a.nx - 1) >> 6; bl = (a.nx - 1) & 63; }
-                if (wl >= 0) {
-                    const uint64_t lb = bits[row + wl];
-                    lf = (lb >> bl) & 1;
-                    lidx = wbase[row + wl] + (uint32_t)__popcll(lb & ((1ull << bl) - 1ull));
-                }
-                int wr = -1;
-                if (x0 + 64 < a.nx) wr = seg + 1;
-                else if (a.per[0]) wr = 0;
-                if (wr >= 0) {
-                    rf = bits[row + wr] & 1;
-                    ridx = wbase[row + wr];
-                }
-            }
-            const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(mb >> 32),
-                                                            __builtin_amdgcn_mbcnt_lo((uint32_t)mb, 0u));
-            const bool fm = (mb >> lane) & 1;
-            const bool fL = lane > 0 ? ((mb >> (lane - 1)) & 1) : lf;
-            const bool fR = !last ? ((mb >> (lane + 1)) & 1) : rf;
-            const int r = (dy + 1) + 3 * (dz + 1);
-            nbf |= (fL ? 1u : 0u) << (3 * r + 0);
-            nbf |= (fm ? 1u : 0u) << (3 * r + 1);
-            nbf |= (fR ? 1u : 0u) << (3 * r + 2);
-            im[r] = mbase + rank;
-            li[r] = lidx;
-            ri[r] = ridx;
-        }
+    for (int r = 0; r < 9; ++r) {
+        if (D == 2 && r / 3 != 1) continue;
+        const uint64_t mb = rb[r] & keep;
+        const uint64_t lf = (wave_in && rl[r] != kNoSlot) ? 1ull : 0ull;
+        const uint64_t rf = (wave_in && rr[r] != kNoSlot) ? 1ull : 0ull;
+        // bit lane of lw / mb / rw: fluid flag of x - 1 / x / x + 1
+        const uint64_t lw = (mb << 1) | lf;
+        const uint64_t rw = (mb >> 1) | (rf << lastbit);
+        const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(mb >> 32),
+                                                        __builtin_amdgcn_mbcnt_lo((uint32_t)mb, 0u));
+        nbf |= (uint32_t)((lw >> lane) & 1u) << (3 * r + 0);
+        nbf |= (uint32_t)((mb >> lane) & 1u) << (3 * r + 1);
+        nbf |= (uint32_t)((rw >> lane) & 1u) << (3 * r + 2);
+        im[r] = rbase[r] + rank;
+        li[r] = rl[r];
+        ri[r] = rr[r];
     }
     // compact index of the neighbour x + (dx, row r) (valid when it is fluid)
     auto nbi = [&](int dx, int r) -> uint32_t {
@@ -651,7 +639,7 @@ static hipError_t go_step(int layout, const StepArgs& a, hipStream_t s)
                                    0, s, a);
         }
     } else if (layout == LAYOUT_COMPACT) {
-        hipLaunchKernelGGL((k_step_compact<LAT, OP, PREC, PAT, MON>), grid, dim3(threads), 0, s, a, a.bits, a.wbase);
+        hipLaunchKernelGGL((k_step_compact<LAT, OP, PREC, PAT, MON>), grid, dim3(threads), 0, s, a, a.recs);
     } else {
         const int hz = (Lattice<LAT>::D == 3) ? a.tz + 2 : 1;
         const size_t sh = (PAT != PAT_AA_LOCAL) ? (size_t)(a.tx + 2) * (a.ty + 2) * hz : 0;

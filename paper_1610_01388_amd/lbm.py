@@ -69,7 +69,7 @@ class lbm_sizes(ctypes.Structure):
 EXPORTS = ["lbm_last_error", "lbm_lattice_info", "lbm_query_sizes", "lbm_create", "lbm_bind",
            "lbm_set_mask", "lbm_init_equilibrium", "lbm_write_populations", "lbm_read_populations",
            "lbm_step", "lbm_time", "lbm_set_monitor_interval", "lbm_read_history", "lbm_monitors",
-           "lbm_set_umax_limit", "lbm_read_moments", "lbm_save", "lbm_load", "lbm_set_tile",
+           "lbm_set_umax_limit", "lbm_read_moments", "lbm_save", "lbm_load", "lbm_check_checkpoint", "lbm_set_tile",
            "lbm_get_tile", "lbm_set_tile_order", "lbm_get_tile_order", "lbm_set_pull_form", "lbm_get_pull_form",
            "lbm_autotune", "lbm_destroy",
            "lbm_batch_query_sizes", "lbm_batch_create", "lbm_batch_bind", "lbm_batch_init_equilibrium",
@@ -120,6 +120,8 @@ def load_library(path: str = LIB_PATH):
         "lbm_read_moments": ([vp, dp, dp, dp, u8p], ctypes.c_int),
         "lbm_save": ([vp, vp, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
         "lbm_load": ([vp, vp, ctypes.c_size_t], ctypes.c_int),
+        "lbm_check_checkpoint": ([ctypes.POINTER(lbm_desc), ctypes.POINTER(lbm_rheology), vp, ctypes.c_size_t],
+                                 ctypes.c_int),
         "lbm_set_tile": ([vp, i32, i32, i32], ctypes.c_int),
         "lbm_get_tile": ([vp, i32p, i32p, i32p], ctypes.c_int),
         "lbm_set_tile_order": ([vp, i32, i32], ctypes.c_int),
@@ -277,6 +279,13 @@ def lbm_save(h):
 def lbm_load(h, blob: bytes):
     buf = ctypes.create_string_buffer(blob, len(blob))
     _check(load_library().lbm_load(h, buf, len(blob)))
+
+
+def lbm_check_checkpoint(desc, rh, blob: bytes):
+    """Validate a checkpoint blob for a domain of this descriptor and
+    rheology on the host (no device); raises LbmError when it is rejected."""
+    buf = ctypes.create_string_buffer(blob, len(blob))
+    _check(load_library().lbm_check_checkpoint(ctypes.byref(desc), ctypes.byref(rh), buf, len(blob)))
 
 
 def lbm_set_tile(h, tx, ty, tz):

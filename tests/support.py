@@ -38,9 +38,10 @@ def random_mask(N, seed, fraction):
 
 def run_pair(lat, dims, periodic, op, steps, *, nu_p=0.1, sigma_y=5e-4, m=1e4, g=(2e-5, -1e-5, 5e-6),
              lam=0.25, scheme="AA", precision="FP64", mask=None, seed=1, amp=1e-2, tile=None,
-             gpu_kw=None, flow_axis=0, mrt_bulk=0.0, mrt_even=0.0, pull_form=None, hb_n=1.0):
+             gpu_kw=None, flow_axis=0, mrt_bulk=0.0, mrt_even=0.0, pull_form=None, hb_n=1.0, hist=None):
     """Run the oracle and the library from the same seeded state; return both
-    moment sets (and the populations read back)."""
+    moment sets (and the populations read back).  With a list hist, the
+    library's fused monitor records of every step are appended to it."""
     from paper_1610_01388_amd import lbm
     N = int(np.prod(dims))
     g = tuple(g[a] if (a < 2 or lat != 0) else 0.0 for a in range(3))
@@ -68,7 +69,11 @@ def run_pair(lat, dims, periodic, op, steps, *, nu_p=0.1, sigma_y=5e-4, m=1e4, g
         dom.set_pull_form(pull_form)
         assert dom.pull_form() == pull_form
     dom.write_populations(P0[perm], tau0 if op == "PR" else None)
+    if hist is not None:
+        dom.set_monitor_interval(1)
     dom.step(steps)
+    if hist is not None:
+        hist.extend(dom.history())
     got = dom.moments()
     Pg, taug = dom.read_populations(with_tau=(op == "PR"))
     dom.close()

@@ -28,7 +28,7 @@ def test_reduced_precision_vs_oracle(lat, op, precision):
     mask = random_mask(N, 300 + lat, 0.15)
     kw = {"layout": "COMPACT"}
     if precision == "FP16":
-        kw.update(fp64_fallback=True, fallback_band=0.05 if op == "IR" else 1.0, fp16_scale_log2=14)
+        kw.update(fp64_fallback=True, fallback_band=0.05 if op == "IR" else 0.5, fp16_scale_log2=14)
     ref, got, _, _ = run_pair(lat, dims, per, op, 60, mask=mask, seed=11, gpu_kw=kw, precision=precision)
     fluid = mask == 0
     print(f"{LAT_NAMES[lat]} {op} {precision}: u L2-rel {l2rel(got[1], ref[1]):.2e}, "
@@ -43,15 +43,18 @@ def test_reduced_precision_vs_oracle(lat, op, precision):
 def test_fp32_with_fallback_vs_oracle(lat, op, form):
     """FP32 storage with the FP64 redo compiled in (kernels of their own):
     every lattice, both operators, both compact neighbour kernels and A/B,
-    against the FP64 oracle at the FP32 bars."""
+    against the FP64 oracle at the FP32 bars; the redo is seen to run (the
+    fused monitors count the nodes it took)."""
     scheme, pull = form
     dims = {0: (70, 37, 1), 1: (70, 13, 9), 2: (37, 11, 13)}[lat]
     per = (1, 0, 1)
     N = int(np.prod(dims))
     mask = random_mask(N, 310 + lat, 0.15)
-    kw = {"layout": "COMPACT", "fp64_fallback": True, "fallback_band": 0.5 if op == "IR" else 1.0}
+    kw = {"layout": "COMPACT", "fp64_fallback": True, "fallback_band": 0.5}
+    hist = []
     ref, got, _, _ = run_pair(lat, dims, per, op, 40, mask=mask, seed=13, gpu_kw=kw, precision="FP32", scheme=scheme,
-                              pull_form=pull)
+                              pull_form=pull, hist=hist)
+    assert len(hist) == 40 and sum(h["fallback"] for h in hist) > 0
     fluid = mask == 0
     assert l2rel(got[1], ref[1]) <= PREC_TOL["FP32"]["u"]
     assert np.max(np.abs(got[0] - ref[0])[fluid]) <= PREC_TOL["FP32"]["rho"]

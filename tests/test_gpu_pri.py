@@ -39,7 +39,7 @@ def test_pri_reduced_precision(precision):
     mask = random_mask(N, 91, 0.15)
     kw = {"layout": "COMPACT"}
     if precision == "FP16":
-        kw.update(fp64_fallback=True, fallback_band=1.0, fp16_scale_log2=14)
+        kw.update(fp64_fallback=True, fallback_band=0.5, fp16_scale_log2=14)
     ref, got, _, _ = run_pair(lat, dims, per, "PRI", 60, mask=mask, seed=17, precision=precision, gpu_kw=kw)
     tol = {"FP32": 2e-5, "FP16": 5e-3}[precision]
     assert l2rel(got[1], ref[1]) <= tol
