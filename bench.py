@@ -8,17 +8,19 @@ steps.  One step = one fused stream-collide launch over the whole domain.
 value = fluid-node updates per second (MLUPS) over the timed steps.
 
 Also reported ("forms"): the PR operator, FP32 and FP16 storage (the FP16
-form on the 384^3 pack, seed 2, with the FP64 fallback near the yield
-surface), the 4x128x128 D3Q19 duct, and the batched duct sweep, each with
-its velocity/flux/plug-volume error against an FP64 run of the same input;
-and the creeping-flow cylinder cell of the paper's Table 2 run to steady
-state, with its similarity numbers against the printed ones.
+forms on the 384^3 pack, seed 2, without and with the FP64 redo of nodes near
+the yield stress), the 4x128x128 D3Q19 duct, and the batched duct sweep, each
+with its velocity/flux/plug-volume error against an FP64 run of the same
+input at a fixed step (--accuracy-steps from rest, whatever --steps is); and
+the creeping-flow cylinder cell of the paper's Table 2 run to steady state,
+with its similarity numbers against the printed ones.
 
 Roofline: algorithmic bytes of the step kernel per launch (fluid nodes x
 2 Q x 8 B, plus 16 B per fluid node of relaxation time for PR) over its
 average duration from HIP events around the timed launches; peak 8 TB/s.
-The CPU baseline is the FP64 oracle (single thread) on two steps of the same
-workload.
+The CPU baseline is the FP64 oracle on the host cores (all of them, and one)
+on a few steps of the same workload, with the host's core count and CPU
+model.
 """
 from __future__ import annotations
 
@@ -35,6 +37,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FORM_GROUPS = ("fp64", "tight", "box", "ab", "lattices", "fp32", "fp16", "duct", "batch", "cylinder")
 METRIC = "MLUPS and achieved HBM GB/s (% of peak) vs FP64 form at stated velocity error"
 Q = {"D2Q9": 9, "D3Q19": 19, "D3Q27": 27}
 PREC_BYTES = {"FP64": 8, "FP32": 4, "FP16": 2}
@@ -103,8 +106,16 @@ def compare(ref, got, axis):
             "unyielded_ref": pr, "unyielded": pg}
 
 
-def run_form(torch, lbm, name, case, precision, mask, fluid, warmup, steps, ref=None, **kw):
+def run_form(torch, lbm, name, case, precision, mask, fluid, warmup, steps, ref=None, develop=0, **kw):
+    """One bench form: from rest, `develop` untimed steps, the moments at that
+    time (the accuracy snapshot, compared with `ref` when given), then
+    `warmup` untimed and `steps` timed steps.  The snapshot horizon does not
+    depend on the timed step count."""
     dom = make_domain(lbm, case, precision, mask=mask, **kw)
+    mom = None
+    if develop:
+        dom.step(develop)
+        mom = dom.moments()
     ms, wall = timed_run(torch, dom, warmup, steps)
     mlups = fluid * steps / (ms * 1e-3) / 1e6
     bpn = algorithmic_bytes_per_node(case["lattice"], case["op"], precision)
@@ -113,9 +124,12 @@ def run_form(torch, lbm, name, case, precision, mask, fluid, warmup, steps, ref=
            "dims": list(case["dims"]), "fluid_nodes": int(fluid), "steps": steps,
            "ms_per_step": ms / steps, "MLUPS": mlups, "algorithmic_GBs": gbs,
            "hbm_frac": gbs / HBM_PEAK_GBS, "bytes_per_node": bpn}
+    if kw.get("fp64_fallback"):
+        out["fallback_band"] = kw.get("fallback_band")
     if kw.get("layout", "COMPACT") == "COMPACT":
         out["neighbour_kernel"] = dom.pull_form()
-    mom = dom.moments()
+    if mom is None:
+        mom = dom.moments()
     hist = dom.history()
     if hist:
         out["last_monitor"] = {"step": hist[-1]["step"], "flux": float(hist[-1]["flux"][0]),
@@ -123,6 +137,7 @@ def run_form(torch, lbm, name, case, precision, mask, fluid, warmup, steps, ref=
                                "unyielded": int(hist[-1]["unyielded"])}
     if ref is not None:
         out["error_vs_fp64"] = compare(ref, mom, int(np.argmax(np.abs(case["g"]))))
+        out["error_vs_fp64"]["at_step"] = develop
     dom.close()
     torch.cuda.empty_cache()
     return out, mom
@@ -170,6 +185,48 @@ def darcy_sweep(torch, lbm, inputs, n, bis, ops, cap):
                 dom.close()
                 torch.cuda.empty_cache()
             row["fp32_error_vs_fp64"] = compare(mom["FP64"], mom["FP32"], 0)
+            print(json.dumps(row), flush=True)
+
+
+def precision_study(torch, lbm, inputs, n, horizons, bands):
+    """Reduced precision against FP64 on the porous workload (seed 2) at
+    several times from rest: FP32, FP16 without the FP64 redo, and FP16 with
+    the redo of nodes within each relative band around the yield stress.  One
+    JSON line per (operator, form): the errors at each horizon, the share of
+    nodes the redo took at the last one, and ms per step."""
+    mask, _ = inputs.sphere_pack((n, n, n), 8.0, 0.7, seed=2)
+    fluid = int((mask == 0).sum())
+    forms = [("FP32", {}), ("FP16", {})] + [("FP16", {"fp64_fallback": True, "fallback_band": b}) for b in bands]
+    for op in ("IR", "PR"):
+        case = inputs.porous_case(op, n=n, Bi=1.0, m=1e4)
+        snaps = {}
+        dom = make_domain(lbm, case, "FP64", mask=mask)
+        done = 0
+        for hz in horizons:
+            dom.step(hz - done)
+            done = hz
+            snaps[hz] = dom.moments()
+        dom.close()
+        torch.cuda.empty_cache()
+        log(f"precision study {op}: FP64 reference to step {horizons[-1]}")
+        for prec, kw in forms:
+            dom = make_domain(lbm, case, prec, mask=mask, fp16_scale_log2=14, **kw)
+            dom.set_monitor_interval(100)
+            row = {"study": f"D3Q27 {n}^3 sphere pack (seed 2), Bi 1, from rest", "operator": op, "precision": prec,
+                   "fp64_redo_band": kw.get("fallback_band"), "fluid_nodes": fluid, "errors": {}}
+            done = 0
+            for hz in horizons:
+                dom.step(hz - done)
+                done = hz
+                row["errors"][str(hz)] = compare(snaps[hz], dom.moments(), 0)
+            hist = dom.history()
+            row["redo_share_last"] = hist[-1]["fallback"] / fluid if hist else None
+            row["unyielded_share_last"] = hist[-1]["unyielded"] / fluid if hist else None
+            ms, _ = timed_run(torch, dom, 0, 200)
+            row["ms_per_step"] = ms / 200
+            row["MLUPS"] = fluid * 200 / (ms * 1e-3) / 1e6
+            dom.close()
+            torch.cuda.empty_cache()
             print(json.dumps(row), flush=True)
 
 
@@ -270,22 +327,88 @@ def cylinder_form(torch, lbm, inputs):
             "rel_error": {k: abs(got[k] - want[k]) / want[k] for k in want}}
 
 
-def cpu_baseline(case, mask, fluid, steps=2):
-    """The FP64 oracle (single thread, as it stands) on a few steps of the
-    same workload (about 15 s of CPU work)."""
+def host_description():
+    """Host cores and CPU model of the machine the CPU baseline runs on."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"nproc": os.cpu_count(), "usable_cpus": usable, "cpu_model": model,
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
+
+
+def oracle_threads():
+    """All host cores the process may use (OMP_NUM_THREADS caps it)."""
+    host = host_description()
+    n = host["usable_cpus"] or 1
+    if host["omp_num_threads"]:
+        try:
+            n = min(n, int(host["omp_num_threads"]))
+        except ValueError:
+            pass
+    return max(1, n)
+
+
+def time_oracle(case, mask, steps, threads):
+    """MLUPS of the FP64 oracle (as it stands) on `steps` steps of a case."""
     import oracle
-    op = {"PR": oracle.PR, "IR": oracle.IR}[case["op"]]
+    op = {"PR": oracle.PR, "IR": oracle.IR, "PRI": oracle.PRI}[case["op"]]
     lat = {"D2Q9": 0, "D3Q19": 1, "D3Q27": 2}[case["lattice"]]
     rh = oracle.rheology(op, case["nu_p"], case["sigma_y"], case["m"], 1e-8, 0.25, case["g"])
+    used = oracle.set_threads(threads)
     od = oracle.Domain(lat, case["dims"], case["periodic"], rh, mask)
+    fluid = int(np.prod(case["dims"])) if mask is None else int((np.asarray(mask) == 0).sum())
     t0 = time.perf_counter()
     od.step(steps)
     dt = time.perf_counter() - t0
     od.close()
-    return {"value": fluid * steps / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
-            "sample": f"{steps} steps of the full {case['dims'][0]}x{case['dims'][1]}x{case['dims'][2]} "
-                      f"{case['lattice']} {case['op']} workload ({fluid} fluid nodes), "
-                      f"{dt:.1f} s single-threaded FP64 C"}
+    return fluid * steps / dt / 1e6, dt, used
+
+
+def cpu_baseline(case, mask, fluid):
+    """The FP64 oracle (as it stands) on the host cores: one step of the main
+    workload on one thread and four steps on every core the process may use
+    (about 10-20 s of CPU work in all)."""
+    host = host_description()
+    one, dt1, _ = time_oracle(case, mask, 1, 1)
+    nthr = oracle_threads()
+    allc, dtn, used = time_oracle(case, mask, 4, nthr)
+    dims = "x".join(str(v) for v in case["dims"])
+    return {"value": allc, "unit": "MLUPS", "cores": used, "kind": "oracle",
+            "single_core_value": one, "host": host,
+            "sample": f"the full {dims} {case['lattice']} {case['op']} FP64 workload ({fluid} fluid nodes): "
+                      f"1 step on 1 thread ({dt1:.1f} s) and 4 steps on {used} threads ({dtn:.1f} s), "
+                      "plain C with OpenMP over rows, results identical for any thread count"}
+
+
+def cpu_configs(inputs):
+    """The oracle on the two small configurations in full: the D2Q9 4x64
+    Bingham channel (20 000 steps, IR and PR) and the D3Q19 4x128x128 duct
+    (Bi 0.5, 50 000 steps, IR; all cores in full, one thread over a 1 000-step
+    window).  One JSON line each."""
+    host = host_description()
+    nthr = oracle_threads()
+    for op in ("IR", "PR"):
+        c = inputs.channel_case(op, H=64, nx=4, Bi=1.0)
+        one, dt1, _ = time_oracle(c, None, 20000, 1)
+        allc, dtn, used = time_oracle(c, None, 20000, nthr)
+        print(json.dumps({"cpu_config": "D2Q9 4x64 Bingham channel, Bi 1, 20000 steps", "operator": op,
+                          "MLUPS_1_thread": one, "seconds_1_thread": dt1, "MLUPS_all": allc, "seconds_all": dtn,
+                          "threads": used, "host": host}), flush=True)
+    duct = inputs.duct_case("IR", side=128, length=4, Bi=0.5)
+    allc, dtn, used = time_oracle(duct, None, 50000, nthr)
+    one, dt1, _ = time_oracle(duct, None, 1000, 1)
+    print(json.dumps({"cpu_config": "D3Q19 4x128x128 square duct, Bi 0.5, IR", "MLUPS_all_50000_steps": allc,
+                      "seconds_all": dtn, "threads": used, "MLUPS_1_thread_1000_steps": one, "seconds_1_thread": dt1,
+                      "host": host}), flush=True)
 
 
 def traffic_from_profile(kernel_hash, per_launch_bytes):
@@ -311,6 +434,16 @@ def main():
     ap.add_argument("--size", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-forms", action="store_true", help="main line only")
+    ap.add_argument("--only", default=None,
+                    help="comma-separated form groups to run (default: all): " + ",".join(FORM_GROUPS))
+    ap.add_argument("--accuracy-steps", type=int, default=1000,
+                    help="steps from rest at which reduced-precision forms are compared with FP64")
+    ap.add_argument("--precision-study", action="store_true",
+                    help="instead of the throughput line: FP32 and FP16 (without and with the FP64 redo in several "
+                         "bands) against FP64 at several times from rest on the --size pack (seed 2)")
+    ap.add_argument("--study-steps", default="1000,5000,20000", help="horizons of --precision-study")
+    ap.add_argument("--cpu-configs", action="store_true",
+                    help="instead of the throughput line: time the oracle on the two small configurations in full")
     ap.add_argument("--batch-only", action="store_true",
                     help="only the batched sweep form (for profiling its kernel)")
     ap.add_argument("--layout", default="COMPACT", choices=["COMPACT", "DENSE"],
@@ -327,9 +460,19 @@ def main():
               "is not implemented", file=sys.stderr)
         sys.exit(2)
 
+    if args.cpu_configs:
+        from paper_1610_01388_amd import inputs
+        cpu_configs(inputs)
+        return
+
     import torch
     from paper_1610_01388_amd import inputs, lbm
     torch.cuda.set_device(0)
+
+    if args.precision_study:
+        precision_study(torch, lbm, inputs, args.size, [int(v) for v in args.study_steps.split(",")],
+                        (0.02, 0.05, 0.2))
+        return
 
     if args.darcy:
         darcy_sweep(torch, lbm, inputs, args.size, (0.1, 0.316, 1.0, 3.16, 10.0), ("IR", "PR"), args.darcy_cap)
@@ -366,7 +509,6 @@ def main():
     tile = dom.tile()
     nk = dom.pull_form() if args.layout == "COMPACT" else None
     ms, wall = timed_run(torch, dom, args.warmup, args.steps)
-    ref_ir = dom.moments()
     hist = dom.history()
     dom.close()
     torch.cuda.empty_cache()
@@ -407,20 +549,30 @@ def main():
                                             "unyielded": int(hist[-1]["unyielded"])}
 
     forms = []
-    if not args.no_forms:
-        W, K = args.warmup, min(args.steps, 500)
-        log("forms: FP64 references (compact layout) and the dense layout")
-        f64_ir, ref_ir = run_form(torch, lbm, "IR FP64", case, "FP64", mask, fluid, W, K)
-        f64_pr, ref_pr = run_form(torch, lbm, "PR FP64", case_pr, "FP64", mask, fluid, W, K)
-        dense_ir, _ = run_form(torch, lbm, "IR FP64 dense layout", case, "FP64", mask, fluid, W, K, ref=ref_ir,
-                               layout="DENSE")
+    groups = set(FORM_GROUPS if args.only is None else args.only.split(","))
+    unknown = groups - set(FORM_GROUPS)
+    if unknown:
+        sys.exit(f"bench.py: unknown form groups {sorted(unknown)}; known: {','.join(FORM_GROUPS)}")
+    if args.no_forms:
+        groups = set()
+    W, K, H = args.warmup, min(args.steps, 500), args.accuracy_steps
+    ref_ir = ref_pr = None
+    if groups & {"fp64", "fp32", "ab"}:
+        log(f"forms: FP64 references (compact layout), accuracy snapshot at step {H}")
+        f64_ir, ref_ir = run_form(torch, lbm, "IR FP64", case, "FP64", mask, fluid, W, K, develop=H)
+        f64_pr, ref_pr = run_form(torch, lbm, "PR FP64", case_pr, "FP64", mask, fluid, W, K, develop=H)
+        forms += [f64_ir, f64_pr]
+    if "fp64" in groups:
+        log("forms: dense layout, PRI, IRHB")
+        forms.append(run_form(torch, lbm, "IR FP64 dense layout", case, "FP64", mask, fluid, W, K, ref=ref_ir,
+                              develop=H, layout="DENSE")[0])
         case_pri = dict(case_pr, op="PRI")
-        pri, _ = run_form(torch, lbm, "PRI FP64 (implicit tau update, no tau field)", case_pri, "FP64", mask, fluid,
-                          W, K)
+        forms.append(run_form(torch, lbm, "PRI FP64 (implicit tau update, no tau field)", case_pri, "FP64", mask,
+                              fluid, W, K)[0])
         case_hb = dict(case, op="IRHB")
-        hb, _ = run_form(torch, lbm, "IRHB FP64 (Herschel-Bulkley, n = 0.5, K = nu_p)", case_hb, "FP64", mask, fluid,
-                         W, K, hb_n=0.5)
-        forms += [f64_ir, f64_pr, dense_ir, pri, hb]
+        forms.append(run_form(torch, lbm, "IRHB FP64 (Herschel-Bulkley, n = 0.5, K = nu_p)", case_hb, "FP64", mask,
+                              fluid, W, K, hb_n=0.5)[0])
+    if "tight" in groups:
         log("forms: tight medium (overlapping spheres, porosity 0.15): row-segment vs slot neighbour kernel")
         mask_t, _ = inputs.overlapping_spheres((n, n, n), 8.0, 0.15, seed=1)
         fl_t = int((mask_t == 0).sum())
@@ -430,12 +582,16 @@ def main():
                                  fl_t, W, K, ref=ref_t)
         forms += [tight_rows, tight_auto]
         del ref_t, mask_t
+    if "box" in groups:
         log("forms: all-fluid periodic box of the same size (ceiling of this access pattern)")
         forms.append(run_form(torch, lbm, "IR FP64 all-fluid periodic box (ceiling)", case, "FP64",
                               np.zeros(n ** 3, dtype=np.uint8), n ** 3, W, K)[0])
-        log("forms: A/B streaming, and the D3Q19 and D2Q9 lattices at HBM scale")
+    if "ab" in groups:
+        log("forms: A/B streaming")
         forms.append(run_form(torch, lbm, "IR FP64 A/B streaming (two copies)", case, "FP64", mask, fluid, W, K,
-                              ref=ref_ir, scheme="AB")[0])
+                              ref=ref_ir, develop=H, scheme="AB")[0])
+    if "lattices" in groups:
+        log("forms: the D3Q19 and D2Q9 lattices at HBM scale")
         case19 = dict(case, lattice="D3Q19")
         forms.append(run_form(torch, lbm, "IR FP64 D3Q19, same pack", case19, "FP64", mask, fluid, W, K)[0])
         cell = inputs.cylinder_case("IR", sigma_y=1e-5)
@@ -446,40 +602,45 @@ def main():
                               f"({80 * tiles}^2, Table 2 cell)", case2, "FP64", mask2, int((mask2 == 0).sum()),
                               W, K)[0])
         del mask2
-        log("forms: FP32 storage and collision")
-        forms.append(run_form(torch, lbm, "IR FP32", case, "FP32", mask, fluid, W, K, ref=ref_ir)[0])
-        forms.append(run_form(torch, lbm, "PR FP32", case_pr, "FP32", mask, fluid, W, K, ref=ref_pr)[0])
-        del ref_ir, ref_pr
+    if "fp32" in groups:
+        log(f"forms: FP32 storage and collision, errors at step {H}")
+        forms.append(run_form(torch, lbm, "IR FP32", case, "FP32", mask, fluid, W, K, ref=ref_ir, develop=H)[0])
+        forms.append(run_form(torch, lbm, "PR FP32", case_pr, "FP32", mask, fluid, W, K, ref=ref_pr, develop=H)[0])
+    del ref_ir, ref_pr
+    if "fp16" in groups:
         n4 = 384 if n == 256 else n
-        log(f"forms: FP16 storage with FP64 fallback, {n4}^3 pack (seed 2)")
+        log(f"forms: FP16 storage without and with the FP64 redo near the yield stress, {n4}^3 pack (seed 2), "
+            f"errors at step {H}")
         mask4, _ = inputs.sphere_pack((n4, n4, n4), 8.0, 0.7, seed=2)
         fl4 = int((mask4 == 0).sum())
-        c4_ir = inputs.porous_case("IR", n=n4, Bi=1.0)
-        c4_pr = inputs.porous_case("PR", n=n4, Bi=1.0, m=1e4)
-        r64, ref4 = run_form(torch, lbm, f"IR FP64 {n4}^3", c4_ir, "FP64", mask4, fl4, W, K)
-        forms.append(r64)
-        forms.append(run_form(torch, lbm, f"IR FP16+fallback {n4}^3", c4_ir, "FP16", mask4, fl4, W, K, ref=ref4,
-                              fp64_fallback=True, fallback_band=0.05, fp16_scale_log2=14)[0])
-        del ref4
-        r64, ref4 = run_form(torch, lbm, f"PR FP64 {n4}^3", c4_pr, "FP64", mask4, fl4, W, K)
-        forms.append(r64)
-        forms.append(run_form(torch, lbm, f"PR FP16+fallback {n4}^3", c4_pr, "FP16", mask4, fl4, W, K, ref=ref4,
-                              fp64_fallback=True, fallback_band=1.0, fp16_scale_log2=14)[0])
-        del ref4, mask4
+        for op in ("IR", "PR"):
+            c4 = inputs.porous_case(op, n=n4, Bi=1.0, m=1e4)
+            r64, ref4 = run_form(torch, lbm, f"{op} FP64 {n4}^3", c4, "FP64", mask4, fl4, W, K, develop=H)
+            forms.append(r64)
+            forms.append(run_form(torch, lbm, f"{op} FP16 {n4}^3", c4, "FP16", mask4, fl4, W, K, ref=ref4,
+                                  develop=H, fp16_scale_log2=14)[0])
+            forms.append(run_form(torch, lbm, f"{op} FP16 + FP64 redo within 5% of the yield stress {n4}^3", c4,
+                                  "FP16", mask4, fl4, W, K, ref=ref4, develop=H, fp64_fallback=True,
+                                  fallback_band=0.05, fp16_scale_log2=14)[0])
+            del ref4
+        del mask4
+    if "duct" in groups:
         log("forms: D3Q19 4x128x128 duct (cache-resident: MLUPS only)")
         duct = inputs.duct_case("IR", side=128, length=4, Bi=0.5)
         dfl = 128 * 128 * 4
-        d64, dref = run_form(torch, lbm, "duct D3Q19 IR FP64", duct, "FP64", None, dfl, W, K)
-        d32, _ = run_form(torch, lbm, "duct D3Q19 IR FP32", duct, "FP32", None, dfl, W, K, ref=dref)
+        d64, dref = run_form(torch, lbm, "duct D3Q19 IR FP64", duct, "FP64", None, dfl, W, K, develop=H)
+        d32, _ = run_form(torch, lbm, "duct D3Q19 IR FP32", duct, "FP32", None, dfl, W, K, ref=dref, develop=H)
         forms += [d64, d32]
+    if "batch" in groups:
         log("forms: batched sweep, 256 D3Q19 ducts (sides 32..160, length 4), FP32 vs FP64, 1000-step graph")
         forms.append(batch_form(torch, lbm, inputs.batch_sweep(), 1000, 1000))
+    if "cylinder" in groups:
         log("forms: cylinder-array validation cell (Table 2), rest to steady state")
         forms.append(cylinder_form(torch, lbm, inputs))
     result["forms"] = forms
 
     if not args.no_cpu:
-        log("cpu baseline: oracle, two steps of the main workload")
+        log("cpu baseline: oracle on one thread and on all host cores, main workload")
         result["cpu_baseline"] = cpu_baseline(case, mask, fluid)
     else:
         result["cpu_baseline"] = None

@@ -210,8 +210,21 @@ int lbm_init_equilibrium(lbm_domain* dom, double rho0, const double* u0);
 int lbm_write_populations(lbm_domain* dom, const double* host_P, const double* host_tau);
 int lbm_read_populations(lbm_domain* dom, double* host_P, double* host_tau);
 
-/* Enqueue nsteps time steps (asynchronous). */
+/* Enqueue nsteps time steps (asynchronous).  With graph steps G > 0 (see
+ * lbm_set_graph_steps), runs of G steps that start at a time that is a
+ * multiple of G, from the post-collision state in the first copy (A/B) or the
+ * even AA phase, replay one captured hipGraph of G launches; the other steps
+ * launch eagerly.  Results are identical either way. */
 int lbm_step(lbm_domain* dom, int64_t nsteps);
+/* Steps per captured graph (even, >= 0; 0, the default, launches every step
+ * eagerly).  The graph is captured on first use on a private stream of the
+ * default priority and captured again after any change to what the launches
+ * carry (tile, tile order, neighbour-phase kernel, mask, monitor interval,
+ * checkpoint load).  It pays for small domains, whose steps are short enough
+ * for the launch overhead to matter.  With monitors, G must be a multiple of
+ * the monitor interval for replays to be used.  LBM_EINVAL for an odd or
+ * negative count. */
+int lbm_set_graph_steps(lbm_domain* dom, int32_t steps);
 
 /* Current time (number of collisions done). */
 int lbm_time(lbm_domain* dom, int64_t* t);

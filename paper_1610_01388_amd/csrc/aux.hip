@@ -84,72 +84,88 @@ __device__ __forceinline__ void gather(const NodeArgs& a, int64_t k, int x, int 
     }
 }
 
-// Readout of the current state: per-node moments into staging
-// (out[0..count) rho, out[count..4count) u component-major, out[4count..5count)
-// nu_app; out_flags unyielded), or per-block monitor partials.
+// Moments of node n0 + j of the current state: false for a solid node (or j
+// past the range), else true with rho, the output velocity uo and the
+// rheology state pr.
 template <int LAT, int OP, int PREC>
-__global__ __launch_bounds__(256) void k_readout(const NodeArgs a)
+__device__ __forceinline__ bool node_state(const NodeArgs& a, int64_t j, int64_t& k, Pre<typename Store<PREC>::C>& pr,
+                                           typename Store<PREC>::C (&uo)[3])
 {
     using L = Lattice<LAT>;
     using C = typename Store<PREC>::C;
     using T = typename Store<PREC>::T;
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t n = a.n0 + j;
-    const bool inside = j < a.count;
-    int x = 0, y = 0, z = 0;
-    int64_t k = -1;
-    if (inside) {
-        node_xyz(n, a.nx, a.ny, x, y, z);
-        k = slot_of(a, x, y, z);
-    }
-    const bool active = k >= 0;
+    k = -1;
+    if (j >= a.count) return false;
+    int x, y, z;
+    node_xyz(a.n0 + j, a.nx, a.ny, x, y, z);
+    k = slot_of(a, x, y, z);
+    if (k < 0) return false;
     const Coll<C>& cp = ncoll<C>(a);
-    Moments<C> mo;
+    C h[L::Q];
+    gather<LAT, PREC>(a, k, x, y, z, h);
+    const C tau_prev = has_tau(OP) ? (C)((const T*)a.tau)[k] : C(0);
+    const Moments<C> mo = moments<LAT>(h);
+    pr = rheology<LAT, OP>(mo, cp, tau_prev);
+    out_velocity(mo, pr, cp, uo);
+    return true;
+}
+
+// Readout of the current state: per-node moments into staging
+// (out[0..count) rho, out[count..4count) u component-major, out[4count..5count)
+// nu_app; out_flags unyielded), or (reduce) per-block monitor partials.  The
+// reduction walks the nodes with a grid stride, so a grid smaller than one
+// block per 256 nodes still covers them all (with one block per 256 nodes,
+// every thread takes one node).
+template <int LAT, int OP, int PREC>
+__global__ __launch_bounds__(kMaxBlockThreads) void k_readout(const NodeArgs a)
+{
+    using C = typename Store<PREC>::C;
+    const int64_t j0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     Pre<C> pr;
     C uo[3] = {C(0), C(0), C(0)};
-    if (active) {
-        C h[L::Q];
-        gather<LAT, PREC>(a, k, x, y, z, h);
-        const C tau_prev = has_tau(OP) ? (C)((const T*)a.tau)[k] : C(0);
-        mo = moments<LAT>(h);
-        pr = rheology<LAT, OP>(mo, cp, tau_prev);
-        out_velocity(mo, pr, cp, uo);
-    }
+    int64_t k;
     if (a.reduce) {
         double v[MP_COUNT];
 #pragma unroll
         for (int q = 0; q < MP_COUNT; ++q) v[q] = 0.0;
-        if (active) {
+        for (int64_t j = j0; j < a.count; j += (int64_t)gridDim.x * blockDim.x) {
+            if (!node_state<LAT, OP, PREC>(a, j, k, pr, uo)) continue;
+            double w[MP_COUNT];
+#pragma unroll
+            for (int q = 0; q < MP_COUNT; ++q) w[q] = 0.0;
             const double ux = uo[0], uy = uo[1], uz = uo[2], rho = pr.rho;
             const bool bad = !isfinite(rho) || !isfinite(ux) || !isfinite(uy) || !isfinite(uz);
-            v[MP_UX] = ux;
-            v[MP_UY] = uy;
-            v[MP_UZ] = uz;
-            v[MP_MASS] = rho;
-            v[MP_UMAX] = bad ? INFINITY : sqrt(ux * ux + uy * uy + uz * uz);
-            v[MP_UNYIELDED] = pr.unyielded ? 1.0 : 0.0;
-            v[MP_NONFINITE] = bad ? 1.0 : 0.0;
-            v[MP_FLUID] = 1.0;
-            if (a.uprev) residual_terms(ux, uy, uz, bad, a.uprev + k, a.S, v);
+            w[MP_UX] = ux;
+            w[MP_UY] = uy;
+            w[MP_UZ] = uz;
+            w[MP_MASS] = rho;
+            w[MP_UMAX] = bad ? INFINITY : sqrt(ux * ux + uy * uy + uz * uz);
+            w[MP_UNYIELDED] = pr.unyielded ? 1.0 : 0.0;
+            w[MP_NONFINITE] = bad ? 1.0 : 0.0;
+            w[MP_FLUID] = 1.0;
+            if (a.uprev) residual_terms(ux, uy, uz, bad, a.uprev + k, a.S, w);
+#pragma unroll
+            for (int q = 0; q < MP_COUNT; ++q) v[q] = mp_is_max(q) ? fmax(v[q], w[q]) : v[q] + w[q];
         }
         block_reduce_store<MP_COUNT>(v, a.partials + (int64_t)blockIdx.x * MP_COUNT);
         return;
     }
-    if (!inside) return;
+    const bool active = node_state<LAT, OP, PREC>(a, j0, k, pr, uo);
+    if (j0 >= a.count) return;
     const int64_t c = a.count;
-    a.out[j] = active ? (double)pr.rho : 0.0;
-    a.out[c + j] = active ? (double)uo[0] : 0.0;
-    a.out[2 * c + j] = active ? (double)uo[1] : 0.0;
-    a.out[3 * c + j] = active ? (double)uo[2] : 0.0;
-    a.out[4 * c + j] = active ? (double)pr.nu_app : 0.0;
-    a.out_flags[j] = active ? (uint8_t)pr.unyielded : (uint8_t)0;
+    a.out[j0] = active ? (double)pr.rho : 0.0;
+    a.out[c + j0] = active ? (double)uo[0] : 0.0;
+    a.out[2 * c + j0] = active ? (double)uo[1] : 0.0;
+    a.out[3 * c + j0] = active ? (double)uo[2] : 0.0;
+    a.out[4 * c + j0] = active ? (double)pr.nu_app : 0.0;
+    a.out_flags[j0] = active ? (uint8_t)pr.unyielded : (uint8_t)0;
 }
 
 // Equilibrium f_eq(rho, u0) (Sec. 2.1, Eq. 12) as the post-collision state;
 // stored as deviations from w rho0, in the layout given (0 or 1).  Dense
 // storage also clears the slots of solid nodes.
 template <int LAT, int OP, int PREC>
-__global__ __launch_bounds__(256) void k_init(const NodeArgs a, double rho)
+__global__ __launch_bounds__(kMaxBlockThreads) void k_init(const NodeArgs a, double rho)
 {
     using L = Lattice<LAT>;
     using S = typename Store<PREC>::S;
@@ -184,7 +200,7 @@ __global__ __launch_bounds__(256) void k_init(const NodeArgs a, double rho)
 // Write full populations P (staging: q blocks of count doubles, node order)
 // and tau into storage in layout 0 or 1.  Solid nodes carry no state.
 template <int LAT, int PREC>
-__global__ __launch_bounds__(256) void k_pop_write(const NodeArgs a)
+__global__ __launch_bounds__(kMaxBlockThreads) void k_pop_write(const NodeArgs a)
 {
     using L = Lattice<LAT>;
     using S = typename Store<PREC>::S;
@@ -211,7 +227,7 @@ __global__ __launch_bounds__(256) void k_pop_write(const NodeArgs a)
 // last AA step: P_i(x) sits in slot i of x + c_i, or in slot opp(i) of x when
 // x + c_i is solid or beyond a wall.
 template <int LAT, int PREC>
-__global__ __launch_bounds__(256) void k_pop_read(const NodeArgs a)
+__global__ __launch_bounds__(kMaxBlockThreads) void k_pop_read(const NodeArgs a)
 {
     using L = Lattice<LAT>;
     using S = typename Store<PREC>::S;
@@ -268,7 +284,7 @@ __device__ __forceinline__ void fill_record(MonitorRecord* rec, const double (&r
     rec->du_max = r[MP_DUMAX];
 }
 
-__global__ __launch_bounds__(256) void k_finalize(const double* parts, int64_t np, MonitorRecord* rec,
+__global__ __launch_bounds__(kMaxBlockThreads) void k_finalize(const double* parts, int64_t np, MonitorRecord* rec,
                                                   int64_t step, double ntotal)
 {
     __shared__ double red[256][MP_COUNT];
@@ -300,9 +316,48 @@ __global__ __launch_bounds__(256) void k_finalize(const double* parts, int64_t n
     }
 }
 
+// Fused monitors of a domain: the same reduction, into ring slot
+// (*counter mod capacity), then the counter advances (one block, so the
+// read and the increment need no atomics).  The ring position comes from the
+// device, so a captured graph replayed several times fills consecutive slots.
+__global__ __launch_bounds__(kMaxBlockThreads) void k_finalize_ring(const double* parts, int64_t np, MonitorRecord* ring,
+                                                       int64_t* counter, int capacity, int64_t step, double ntotal)
+{
+    __shared__ double red[256][MP_COUNT];
+    double v[MP_COUNT];
+#pragma unroll
+    for (int k = 0; k < MP_COUNT; ++k) v[k] = 0.0;
+    for (int64_t j = threadIdx.x; j < np; j += 256) {
+#pragma unroll
+        for (int k = 0; k < MP_COUNT; ++k) {
+            const double o = parts[j * MP_COUNT + k];
+            v[k] = mp_is_max(k) ? fmax(v[k], o) : v[k] + o;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < MP_COUNT; ++k) red[threadIdx.x][k] = v[k];
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+#pragma unroll
+            for (int k = 0; k < MP_COUNT; ++k)
+                red[threadIdx.x][k] = mp_is_max(k) ? fmax(red[threadIdx.x][k], red[threadIdx.x + s][k])
+                                                     : red[threadIdx.x][k] + red[threadIdx.x + s][k];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const int64_t c = *counter;
+        MonitorRecord* rec = ring + (c % capacity);
+        rec->step = step;
+        fill_record(rec, red[0], ntotal);
+        *counter = c + 1;
+    }
+}
+
 // Batched monitors: one block per simulation sums its work items' partials
 // in a fixed order into record[(counter mod capacity) * nsims + sim].
-__global__ __launch_bounds__(256) void k_batch_finalize(const double* parts, const BatchSim* sims, int nsims,
+__global__ __launch_bounds__(kMaxBlockThreads) void k_batch_finalize(const double* parts, const BatchSim* sims, int nsims,
                                                         MonitorRecord* records, const int64_t* counter,
                                                         int64_t step, int capacity)
 {
@@ -374,26 +429,27 @@ static hipError_t dispatch_lat_prec(int lat, int prec, F&& f)
 
 static inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
 
-hipError_t launch_readout(int lat, int op, int prec, const NodeArgs& a, hipStream_t s, int64_t* nblocks)
+hipError_t launch_readout(int lat, int op, int prec, const NodeArgs& a, hipStream_t s, int64_t* nblocks,
+                          int64_t max_blocks)
 {
-    if (nblocks) *nblocks = (int64_t)nblk(a.count);
+    int64_t nb = (int64_t)nblk(a.count);
+    if (a.reduce && max_blocks > 0 && nb > max_blocks) nb = max_blocks;  // grid-stride reduction
+    if (nblocks) *nblocks = nb;
     if (a.count == 0) return hipSuccess;
+    const dim3 grid((unsigned)nb);
     return dispatch_lat_prec(lat, prec, [&](auto L, auto P) {
         if (op == OP_PR)
-            hipLaunchKernelGGL((k_readout<decltype(L)::value, OP_PR, decltype(P)::value>), dim3(nblk(a.count)),
-                               dim3(256), 0, s, a);
+            hipLaunchKernelGGL((k_readout<decltype(L)::value, OP_PR, decltype(P)::value>), grid, dim3(256), 0, s, a);
         else if (op == OP_PRI)
-            hipLaunchKernelGGL((k_readout<decltype(L)::value, OP_PRI, decltype(P)::value>), dim3(nblk(a.count)),
-                               dim3(256), 0, s, a);
+            hipLaunchKernelGGL((k_readout<decltype(L)::value, OP_PRI, decltype(P)::value>), grid, dim3(256), 0, s, a);
         else if (op == (OP_PR | OP_MRT))
-            hipLaunchKernelGGL((k_readout<decltype(L)::value, OP_PR | OP_MRT, decltype(P)::value>),
-                               dim3(nblk(a.count)), dim3(256), 0, s, a);
+            hipLaunchKernelGGL((k_readout<decltype(L)::value, OP_PR | OP_MRT, decltype(P)::value>), grid, dim3(256), 0,
+                               s, a);
         else if (op == (OP_PRI | OP_MRT))
-            hipLaunchKernelGGL((k_readout<decltype(L)::value, OP_PRI | OP_MRT, decltype(P)::value>),
-                               dim3(nblk(a.count)), dim3(256), 0, s, a);
+            hipLaunchKernelGGL((k_readout<decltype(L)::value, OP_PRI | OP_MRT, decltype(P)::value>), grid, dim3(256),
+                               0, s, a);
         else  // IR and IRHB: the readout (velocity, yield flag) does not depend on the law's solve
-            hipLaunchKernelGGL((k_readout<decltype(L)::value, OP_IR, decltype(P)::value>), dim3(nblk(a.count)),
-                               dim3(256), 0, s, a);
+            hipLaunchKernelGGL((k_readout<decltype(L)::value, OP_IR, decltype(P)::value>), grid, dim3(256), 0, s, a);
         return hipGetLastError();
     });
 }
@@ -439,6 +495,14 @@ hipError_t launch_finalize(const double* partials, int64_t nparts, void* record,
                            hipStream_t s)
 {
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, partials, nparts, (MonitorRecord*)record, step, ntotal);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize_ring(const double* partials, int64_t nparts, void* ring, int64_t* counter, int capacity,
+                                int64_t step, double ntotal, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_finalize_ring, dim3(1), dim3(256), 0, s, partials, nparts, (MonitorRecord*)ring, counter,
+                       capacity, step, ntotal);
     return hipGetLastError();
 }
 

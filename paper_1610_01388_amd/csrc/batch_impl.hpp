@@ -171,7 +171,7 @@ __device__ __forceinline__ void batch_local(const BatchArgs& a, const BatchSim& 
 // FB: the FP64 redo of near-yield nodes compiled in (reduced precision with
 // the fallback on); without it the kernel holds no FP64 registers.
 template <int LAT, int PREC, int PAT, bool MON, bool FB>
-__global__ __launch_bounds__(256) void k_batch_step(const BatchArgs a)
+__global__ __launch_bounds__(kMaxBlockThreads) void k_batch_step(const BatchArgs a)
 {
     constexpr int F = FB ? OP_FB : 0;
     int hi = a.nitems, first = blockIdx.x, stride = gridDim.x;

@@ -69,7 +69,7 @@ static_assert((int)OP_PR == (int)LBM_PR && (int)OP_IR == (int)LBM_IR && (int)OP_
 constexpr int64_t kStridePad = 32768;
 
 struct Layout {
-    size_t pdf_copy, pdf, tau, mask, part, hist, rec, uprev, stage, work;
+    size_t pdf_copy, pdf, tau, mask, part, hist, rec, counter, uprev, stage, work;
     size_t bits_off, base_off, wstart_off, recs_off, mask_compact;  // compact mask: bitmap, word bases, group
                                                                     // words, segment records
     int64_t max_parts, npad;
@@ -111,7 +111,8 @@ Layout layout_of(const lbm_desc* d, const lbm_rheology* r)
     L.part = 0;
     L.hist = align_up((size_t)L.max_parts * MP_COUNT * sizeof(double));
     L.rec = L.hist + align_up(kHistory * sizeof(MonitorRecord));
-    L.uprev = L.rec + align_up(sizeof(MonitorRecord));
+    L.counter = L.rec + align_up(sizeof(MonitorRecord));
+    L.uprev = L.counter + kAlign;
     L.stage = L.uprev + align_up((size_t)3 * L.npad * sizeof(double));
     size_t stage = std::min(kStageMax, align_up((size_t)N * (Q + 1) * 8));
     stage = std::max(stage, align_up((size_t)(Q + 1) * 8 * 256));
@@ -141,9 +142,16 @@ struct lbm_domain {
     int pull_form = LBM_PULL_AUTO;  // compact neighbour phases: slot or row-segment kernel
     int mon_k = 0;
     int64_t hist_written = 0, hist_read = 0;
+    std::vector<int64_t> hist_time = std::vector<int64_t>(kHistory, 0);  // time of each ring slot's record
     double umax_limit = 0.1;
     int64_t S = 0;   // direction stride of the population arrays
     int64_t Nf = 0;  // fluid nodes
+    // captured-graph stepping: replays of graph_steps launches (0 = eager)
+    int graph_steps = 0;
+    hipGraphExec_t graph = nullptr;
+    hipStream_t cap = nullptr;
+    uint64_t gen = 0;        // bumped by every change to what the step launches bake in
+    uint64_t graph_gen = 0;  // gen the graph was captured at
 };
 
 namespace {
@@ -156,6 +164,7 @@ int ntiles_of(const lbm_domain* dm, int tx, int ty, int tz)
 
 int check_tile(const lbm_domain* dm, int tx, int ty, int tz)
 {
+    static_assert(kMaxBlockThreads == 256, "tile shapes are validated against 256-thread blocks");
     const int th = tx * ty * tz;
     if (tx < 1 || ty < 1 || tz < 1 || (th != 64 && th != 128 && th != 192 && th != 256))
         return fail(LBM_EINVAL, "tile %dx%dx%d: threads must be 64, 128, 192 or 256", tx, ty, tz);
@@ -308,6 +317,7 @@ StepArgs step_args(lbm_domain* dm)
     a.nwords = (int64_t)dm->L.W * dm->d.ny * dm->d.nz;
     a.slot_bpx = (int)(((dm->Nf + 255) / 256 + 7) / 8);
     a.pull_slots = pull_slots(dm) ? 1 : 0;
+    a.buf_rows = 2.0 * (double)dm->S * (double)prec_bytes(dm->d.precision) < 4294967296.0 ? 1 : 0;
     a.partials = (double*)dm->work;
     a.uprev = (double*)(dm->work + dm->L.uprev);
     a.N = dm->N;
@@ -358,7 +368,9 @@ int64_t chunk_nodes(const lbm_domain* dm, size_t bytes_per_node)
     return std::max<int64_t>(1, std::min<int64_t>(dm->N, (int64_t)(stage / bytes_per_node)));
 }
 
-int run_steps(lbm_domain* dm, int64_t nsteps)
+// Enqueue nsteps steps on stream st (the bound stream, or the capture
+// stream while a graph is recorded), advancing the host-side state.
+int run_steps(lbm_domain* dm, int64_t nsteps, hipStream_t st)
 {
     StepArgs a = step_args(dm);
     if (a.ntiles > dm->L.max_parts)
@@ -381,14 +393,17 @@ int run_steps(lbm_domain* dm, int64_t nsteps)
         }
         const bool mon = dm->mon_k > 0 && (dm->t % dm->mon_k) == 0;
         HIPCHK(launch_step(dm->d.lattice, kernel_op(dm->r) | (a.fallback ? OP_FB : 0), dm->d.precision, pat, mon,
-                           dm->d.layout, a, dm->stream));
+                           dm->d.layout, a, st));
         if (mon) {
-            char* rec = dm->work + dm->L.hist + (size_t)(dm->hist_written % kHistory) * sizeof(MonitorRecord);
             // the compact slot kernels run one block per 256 fluid slots, the others one per tile
             const int64_t nparts = (dm->d.layout == LBM_COMPACT && (pat == PAT_AA_LOCAL || a.pull_slots))
                                        ? (dm->Nf + 255) / 256
                                        : a.ntiles;
-            HIPCHK(launch_finalize((double*)dm->work, nparts, rec, dm->t, (double)dm->N, dm->stream));
+            // the record goes to ring slot (device counter mod kHistory), so a
+            // replayed graph fills consecutive slots
+            HIPCHK(launch_finalize_ring((double*)dm->work, nparts, dm->work + dm->L.hist,
+                                        (int64_t*)(dm->work + dm->L.counter), kHistory, dm->t, (double)dm->N, st));
+            dm->hist_time[(size_t)(dm->hist_written % kHistory)] = dm->t;
             dm->hist_written++;
         }
         if (dm->d.scheme == LBM_AB) dm->cur = 1 - dm->cur;
@@ -398,10 +413,59 @@ int run_steps(lbm_domain* dm, int64_t nsteps)
     return LBM_OK;
 }
 
+// The history restarts: host counters and the device ring counter.
+int reset_history(lbm_domain* dm)
+{
+    dm->hist_written = dm->hist_read = 0;
+    HIPCHK(launch_fill_u8((uint8_t*)(dm->work + dm->L.counter), sizeof(int64_t), 0, dm->stream));
+    return LBM_OK;
+}
+
+void drop_graph(lbm_domain* dm)
+{
+    if (dm->graph) (void)hipGraphExecDestroy(dm->graph);
+    dm->graph = nullptr;
+}
+
+// Capture graph_steps steps from the current (replay-start) state into a
+// graph on a private stream; the host state is restored afterwards (a
+// capture runs nothing).
+int build_graph(lbm_domain* dm)
+{
+    drop_graph(dm);
+    if (!dm->cap) HIPCHK(hipStreamCreateWithFlags(&dm->cap, hipStreamNonBlocking));
+    const int64_t t = dm->t, hw = dm->hist_written;
+    const int cur = dm->cur, parity = dm->parity;
+    const std::vector<int64_t> times = dm->hist_time;
+    HIPCHK(hipStreamBeginCapture(dm->cap, hipStreamCaptureModeThreadLocal));
+    const int rc = run_steps(dm, dm->graph_steps, dm->cap);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(dm->cap, &g);
+    dm->t = t;
+    dm->hist_written = hw;
+    dm->cur = cur;
+    dm->parity = parity;
+    dm->hist_time = times;
+    if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(LBM_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    const hipError_t e2 = hipGraphInstantiate(&dm->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e2 != hipSuccess) {
+        dm->graph = nullptr;
+        return fail(LBM_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e2));
+    }
+    dm->graph_gen = dm->gen;
+    return LBM_OK;
+}
+
 // Upload a host mask (nullptr = all fluid) in the domain's layout and set
 // the population stride.
 int upload_mask(lbm_domain* dm, const uint8_t* host_mask)
 {
+    dm->gen++;
     if (dm->d.layout == LBM_DENSE) {
         if (host_mask) {
             // stored as 0 / 1 bytes whatever nonzero value marks a solid
@@ -539,7 +603,7 @@ int lbm_init_equilibrium(lbm_domain* dm, double rho0, const double* u0)
     dm->cur = 0;
     dm->parity = 0;
     dm->t = 0;
-    dm->hist_written = dm->hist_read = 0;
+    if ((rc = reset_history(dm))) return rc;
     NodeArgs a = node_args(dm);
     for (int k = 0; k < 3; ++k) a.u0[k] = u0 ? u0[k] : 0.0;
     HIPCHK(launch_init(dm->d.lattice, dm->r.op, dm->d.precision, a, rho0, dm->stream));
@@ -603,7 +667,42 @@ int lbm_step(lbm_domain* dm, int64_t nsteps)
     int rc = need_bound(dm);
     if (rc) return rc;
     if (nsteps < 0) return fail(LBM_EINVAL, "nsteps must be >= 0");
-    return run_steps(dm, nsteps);
+    const int G = dm->graph_steps;
+    while (nsteps > 0) {
+        // a replay starts from the post-collision state in the first copy, at
+        // a multiple of G, so that its monitor steps fall where they were
+        // captured
+        const bool at_start = dm->d.scheme == LBM_AA ? dm->parity == 0 : dm->cur == 0;
+        const bool graph_ok = G > 0 && nsteps >= G && at_start && dm->t % G == 0 && (dm->mon_k == 0 || G % dm->mon_k == 0);
+        if (!graph_ok) {
+            int64_t n = nsteps;
+            if (G > 0 && dm->t % G != 0) n = std::min<int64_t>(nsteps, G - dm->t % G);
+            if ((rc = run_steps(dm, n, dm->stream))) return rc;
+            nsteps -= n;
+            continue;
+        }
+        if (!dm->graph || dm->graph_gen != dm->gen)
+            if ((rc = build_graph(dm))) return rc;
+        HIPCHK(hipGraphLaunch(dm->graph, dm->stream));
+        for (int64_t k = 0; k < G; ++k) {
+            if (dm->mon_k > 0 && (dm->t + k) % dm->mon_k == 0) {
+                dm->hist_time[(size_t)(dm->hist_written % kHistory)] = dm->t + k;
+                dm->hist_written++;
+            }
+        }
+        dm->t += G;
+        nsteps -= G;
+    }
+    return LBM_OK;
+}
+
+int lbm_set_graph_steps(lbm_domain* dm, int32_t steps)
+{
+    if (!dm) return fail(LBM_EINVAL, "domain is NULL");
+    if (steps < 0 || (steps % 2)) return fail(LBM_EINVAL, "graph steps must be even and >= 0 (0 = no graph)");
+    dm->graph_steps = steps;
+    drop_graph(dm);
+    return LBM_OK;
 }
 
 int lbm_time(lbm_domain* dm, int64_t* t)
@@ -618,6 +717,7 @@ int lbm_set_monitor_interval(lbm_domain* dm, int32_t k)
     if (!dm) return fail(LBM_EINVAL, "domain is NULL");
     if (k < 0) return fail(LBM_EINVAL, "interval must be >= 0");
     dm->mon_k = k;
+    dm->gen++;
     return LBM_OK;
 }
 
@@ -633,6 +733,7 @@ int lbm_read_history(lbm_domain* dm, lbm_monitor* out, int32_t max, int32_t* cou
     for (int64_t k = 0; k < n; ++k) {
         const int64_t slot = (dm->hist_read + k) % kHistory;
         HIPCHK(hipMemcpy(out + k, ring + slot, sizeof(MonitorRecord), hipMemcpyDeviceToHost));
+        out[k].step = dm->hist_time[(size_t)slot];  // a replayed record carries its capture time
     }
     dm->hist_read += n;
     *count = (int32_t)n;
@@ -777,8 +878,7 @@ int lbm_load(lbm_domain* dm, const void* blob, size_t bytes)
     HIPCHK(hipMemcpy(dm->work + dm->L.uprev, v.uprev, v.h.uprev_bytes, hipMemcpyHostToDevice));
     dm->t = v.h.t;
     dm->parity = v.h.parity;
-    dm->hist_written = dm->hist_read = 0;
-    return LBM_OK;
+    return reset_history(dm);
 }
 
 // ---------------------------------------------------------------------------
@@ -792,6 +892,7 @@ int lbm_set_tile(lbm_domain* dm, int32_t tx, int32_t ty, int32_t tz)
     dm->tx = tx;
     dm->ty = ty;
     dm->tz = tz;
+    dm->gen++;
     return LBM_OK;
 }
 
@@ -801,6 +902,7 @@ int lbm_set_tile_order(lbm_domain* dm, int32_t brick_rows, int32_t brick_planes)
     if (brick_rows < 0 || brick_planes < 0) return fail(LBM_EINVAL, "brick sizes must be >= 0 (0 = default)");
     dm->bry = brick_rows;
     dm->brz = brick_planes;
+    dm->gen++;
     return LBM_OK;
 }
 
@@ -822,6 +924,7 @@ int lbm_set_pull_form(lbm_domain* dm, int32_t form)
     if (form != LBM_PULL_AUTO && form != LBM_PULL_SLOTS && form != LBM_PULL_ROWS)
         return fail(LBM_EINVAL, "unknown pull form %d", (int)form);
     dm->pull_form = form;
+    dm->gen++;
     return LBM_OK;
 }
 
@@ -890,9 +993,9 @@ int lbm_autotune(lbm_domain* dm, int32_t trial_steps)
             dm->tz = tz;
         }
         dm->pull_form = c < 0 ? LBM_PULL_SLOTS : LBM_PULL_ROWS;
-        if ((rc = run_steps(dm, 2))) break;
+        if ((rc = run_steps(dm, 2, dm->stream))) break;
         if ((he = hipEventRecord(e0, dm->stream)) != hipSuccess) break;
-        if ((rc = run_steps(dm, trial_steps))) break;
+        if ((rc = run_steps(dm, trial_steps, dm->stream))) break;
         if ((he = hipEventRecord(e1, dm->stream)) != hipSuccess) break;
         if ((he = hipEventSynchronize(e1)) != hipSuccess) break;
         float ms = 0;
@@ -916,6 +1019,7 @@ int lbm_autotune(lbm_domain* dm, int32_t trial_steps)
         dm->tz = cand[best][2];
     }
     if (ok && best >= -1 && dm->d.layout == LBM_COMPACT) dm->pull_form = best < 0 ? LBM_PULL_SLOTS : LBM_PULL_ROWS;
+    dm->gen++;
     const int rc_load = lbm_load(dm, saved.data(), bytes);
     if (he != hipSuccess) return fail(LBM_EHIP, "autotune: %s", hipGetErrorString(he));
     if (rc) return rc;
@@ -926,6 +1030,8 @@ int lbm_destroy(lbm_domain* dm)
 {
     if (!dm) return LBM_OK;
     if (dm->bound && dm->stream) (void)hipStreamSynchronize(dm->stream);
+    drop_graph(dm);
+    if (dm->cap) (void)hipStreamDestroy(dm->cap);
     delete dm;
     return LBM_OK;
 }

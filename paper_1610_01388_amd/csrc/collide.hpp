@@ -74,29 +74,33 @@ __device__ __forceinline__ void add_c(C& acc, C v, int c)
 // Eq. 9: zeroth, first and second moments (of the deviations).
 // Accumulated in C from populations stored as H (the FP64 redo of a
 // reduced-precision node sums its float values in double, no double copy).
+// The velocities come in opposite pairs (i, i + 1 for odd i): the pair's sum
+// carries the even moments (rho, Pi) and its difference the odd one (j), so
+// each pair is combined once.
 template <int LAT, class C, class H>
 __device__ __forceinline__ Moments<C> moments_as(const H (&h)[Lattice<LAT>::Q])
 {
     using L = Lattice<LAT>;
     Moments<C> mo;
-    mo.drho = 0;
+    mo.drho = (C)h[0];
 #pragma unroll
     for (int a = 0; a < 3; ++a) mo.j[a] = 0;
 #pragma unroll
     for (int a = 0; a < 6; ++a) mo.p[a] = 0;
 #pragma unroll
-    for (int i = 0; i < L::Q; ++i) {
-        const C v = (C)h[i];
-        mo.drho += v;
-        add_c<LAT>(mo.j[0], v, L::cx[i]);
-        add_c<LAT>(mo.j[1], v, L::cy[i]);
-        add_c<LAT>(mo.j[2], v, L::cz[i]);
-        add_c<LAT>(mo.p[0], v, L::cx[i] * L::cx[i]);
-        add_c<LAT>(mo.p[1], v, L::cy[i] * L::cy[i]);
-        add_c<LAT>(mo.p[2], v, L::cz[i] * L::cz[i]);
-        add_c<LAT>(mo.p[3], v, L::cx[i] * L::cy[i]);
-        add_c<LAT>(mo.p[4], v, L::cx[i] * L::cz[i]);
-        add_c<LAT>(mo.p[5], v, L::cy[i] * L::cz[i]);
+    for (int i = 1; i < L::Q; i += 2) {
+        const C hp = (C)h[i], hm = (C)h[i + 1];
+        const C sum = hp + hm, dif = hp - hm;
+        mo.drho += sum;
+        add_c<LAT>(mo.j[0], dif, L::cx[i]);
+        add_c<LAT>(mo.j[1], dif, L::cy[i]);
+        add_c<LAT>(mo.j[2], dif, L::cz[i]);
+        add_c<LAT>(mo.p[0], sum, L::cx[i] * L::cx[i]);
+        add_c<LAT>(mo.p[1], sum, L::cy[i] * L::cy[i]);
+        add_c<LAT>(mo.p[2], sum, L::cz[i] * L::cz[i]);
+        add_c<LAT>(mo.p[3], sum, L::cx[i] * L::cy[i]);
+        add_c<LAT>(mo.p[4], sum, L::cx[i] * L::cz[i]);
+        add_c<LAT>(mo.p[5], sum, L::cy[i] * L::cz[i]);
     }
     return mo;
 }
@@ -396,15 +400,27 @@ __device__ __forceinline__ void relax(H (&h)[Lattice<LAT>::Q], const Moments<C>&
             // f_eq(u+g) - f_eq(u) for +c and -c
             const C fs = r.rho * w * (C(4.5) * cg * (C(2) * cu + cg) - C(1.5) * ug);
             const C fa = r.rho * w * C(3) * cg;
-            h[i] = (H)(hi - ns - na + fs + fa);
-            h[k] = (H)(hk - ns + na + fs - fa);
+            // the pair's post-collision symmetric and antisymmetric parts
+            const C ps = hs - ns + fs, pa = ha - na + fa;
+            h[i] = (H)(ps + pa);
+            h[k] = (H)(ps - pa);
         }
     } else {
+        // Per opposite pair (i, i + 1): the equilibrium's even part and the
+        // stress term are shared, the odd part (velocity and force) changes
+        // sign, so h_i = E + O and h_{i+1} = E - O.
         const C* A = r.a;
         const C trA = A[0] + A[1] + A[2];
         const C third = C(1) / C(3);
+        const C trd = trA * third;
+        const C even0 = mo.drho - C(1.5) * r.rho * uu;
+        {
+            const C w = C(L::w[0]);
+            h[0] = (H)(w * even0 + C(4.5) * w * (C(0) - trd));
+        }
+        const C rho3 = C(3) * r.rho, rho15 = C(1.5) * r.rho, rho45 = C(4.5) * r.rho;
 #pragma unroll
-        for (int i = 0; i < L::Q; ++i) {
+        for (int i = 1; i < L::Q; i += 2) {
             const C w = C(L::w[i]);
             C cu = 0, cg = 0;
             add_c<LAT>(cu, u[0], L::cx[i]);
@@ -420,8 +436,10 @@ __device__ __forceinline__ void relax(H (&h)[Lattice<LAT>::Q], const Moments<C>&
             add_c<LAT>(cac, C(2) * A[3], L::cx[i] * L::cy[i]);
             add_c<LAT>(cac, C(2) * A[4], L::cx[i] * L::cz[i]);
             add_c<LAT>(cac, C(2) * A[5], L::cy[i] * L::cz[i]);
-            const C heq = w * (mo.drho + r.rho * (C(3) * cu + C(4.5) * cu * cu - C(1.5) * uu));
-            h[i] = (H)(heq + C(4.5) * w * (cac - trA * third) + C(1.5) * w * r.rho * cg);
+            const C E = w * (even0 + rho45 * cu * cu) + C(4.5) * w * (cac - trd);
+            const C O = w * (rho3 * cu + rho15 * cg);
+            h[i] = (H)(E + O);
+            h[i + 1] = (H)(E - O);
         }
     }
 }

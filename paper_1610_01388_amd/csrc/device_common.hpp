@@ -76,10 +76,14 @@ __device__ __forceinline__ void residual_terms(double ux, double uy, double uz, 
     v[MP_DUMAX] = bad ? INFINITY : sqrt(du2);
 }
 
+// Sum (max for the max-type entries) of v over the block into dst.  One
+// slot of the shared buffer per wavefront: blocks of at most
+// kMaxBlockThreads threads, which every kernel's launch bounds state.
 template <int N>
 __device__ __forceinline__ void block_reduce_store(double (&v)[N], double* dst)
 {
-    __shared__ double red[4][N];
+    static_assert(kMaxBlockThreads % 64 == 0, "whole wavefronts per block");
+    __shared__ double red[kMaxBlockThreads / 64][N];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
 #pragma unroll

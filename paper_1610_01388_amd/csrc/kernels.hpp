@@ -10,6 +10,11 @@
 
 namespace lbm {
 
+// Largest block of any kernel of the library (their launch bounds); the tile
+// shapes the host accepts (64 to 256 threads) and the block reductions'
+// shared buffers are sized by it.
+constexpr int kMaxBlockThreads = 256;
+
 // Streaming patterns.
 //  PAT_AB:        read the post-collision array A by pulling (x - c_i, or the
 //                 node's own opposite slot when x - c_i is solid / a wall),
@@ -69,6 +74,7 @@ struct StepArgs {
     int W;                 // compact: words per row
     int slot_bpx;          // slot kernels: ceil(ceil(nfluid / 256) / 8), blocks per XCD
     int pull_slots;        // compact neighbour phases: 1 slot kernel, 0 row-segment kernel
+    int buf_rows;          // row-segment kernel with 32-bit buffer offsets (2 S storage elements fit in 2^32 bytes)
     int nx, ny, nz;
     int per[3];
     int tx, ty, tz;        // tile shape (threads per block = tx*ty*tz)
@@ -153,8 +159,13 @@ hipError_t launch_batch_finalize(const BatchArgs& a, const int* sims_item0, void
 hipError_t launch_batch_tick(int64_t* counter, hipStream_t s);
 hipError_t launch_finalize(const double* partials, int64_t nparts, void* record, int64_t step, double ntotal,
                            hipStream_t s);
+hipError_t launch_finalize_ring(const double* partials, int64_t nparts, void* ring, int64_t* counter, int capacity,
+                                int64_t step, double ntotal, hipStream_t s);
 hipError_t launch_init(int lat, int op, int prec, const NodeArgs& a, double rho0, hipStream_t s);
-hipError_t launch_readout(int lat, int op, int prec, const NodeArgs& a, hipStream_t s, int64_t* nblocks);
+// max_blocks > 0 caps the grid of a monitor reduction (the nodes are then
+// walked with a grid stride); *nblocks receives the grid (partials written)
+hipError_t launch_readout(int lat, int op, int prec, const NodeArgs& a, hipStream_t s, int64_t* nblocks,
+                          int64_t max_blocks = 0);
 hipError_t launch_pop_write(int lat, int prec, const NodeArgs& a, hipStream_t s);
 hipError_t launch_pop_read(int lat, int prec, const NodeArgs& a, hipStream_t s);
 hipError_t launch_fill_u8(uint8_t* p, int64_t n, uint8_t v, hipStream_t s);

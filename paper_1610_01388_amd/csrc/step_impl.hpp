@@ -108,7 +108,7 @@ __device__ __forceinline__ void monitor_block(bool active, const Moments<C>& mo,
 }
 
 template <int LAT, int OP, int PREC, int PAT, bool MON>
-__global__ __launch_bounds__(256) void k_step(const StepArgs a)
+__global__ __launch_bounds__(kMaxBlockThreads) void k_step(const StepArgs a)
 {
     using L = Lattice<LAT>;
     constexpr int Q = L::Q;
@@ -234,7 +234,7 @@ __global__ __launch_bounds__(256) void k_step(const StepArgs a)
 // flag and slot of its x-1, x, x+1 neighbours in that row from the word's
 // rank below the lane (mbcnt) and single-bit tests.
 template <int LAT, int OP, int PREC, int PAT, bool MON>
-__global__ __launch_bounds__(256) void k_step_compact(const StepArgs a, const SegRec* __restrict__ recs)
+__global__ __launch_bounds__(kMaxBlockThreads) void k_step_compact(const StepArgs a, const SegRec* __restrict__ recs)
 {
     using L = Lattice<LAT>;
     constexpr int Q = L::Q;
@@ -398,6 +398,199 @@ __global__ __launch_bounds__(256) void k_step_compact(const StepArgs a, const Se
         monitor_block<C>(active, mo, pr, cp, used_fb, a.partials + (int64_t)tile * MP_COUNT, a.uprev, k, St);
 }
 
+// Per-lane choice by a wave-uniform lane mask: bit `lane` of mask set gives
+// a, clear gives b -- one v_cndmask_b32 that reads the mask straight from a
+// scalar register pair (no per-lane bit extraction).
+__device__ __forceinline__ uint32_t lane_pick(uint64_t mask, uint32_t a, uint32_t b)
+{
+    uint32_t r;
+    asm("v_cndmask_b32 %0, %1, %2, %3" : "=v"(r) : "v"(b), "v"(a), "s"(mask));
+    return r;
+}
+
+// A wave-uniform 64-bit value marked as such (kept in scalar registers).
+__device__ __forceinline__ uint64_t uniform64(uint64_t v)
+{
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Raw buffer access to population storage: a 32-bit byte offset from the
+// descriptor's base, range-checked against its size (accesses past it read
+// zero and write nothing).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t pop_rsrc(const void* base, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)bytes, 0x00020000);
+}
+template <class S> __device__ __forceinline__ S buf_ld(__amdgpu_buffer_rsrc_t r, uint32_t off);
+template <> __device__ __forceinline__ double buf_ld<double>(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+template <> __device__ __forceinline__ float buf_ld<float>(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+template <> __device__ __forceinline__ _Float16 buf_ld<_Float16>(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    return __builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0));
+}
+typedef uint32_t u32x2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void buf_st(double v, __amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, v), r, off, 0, 0);
+}
+__device__ __forceinline__ void buf_st(float v, __amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, off, 0, 0);
+}
+__device__ __forceinline__ void buf_st(_Float16 v, __amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, off, 0, 0);
+}
+
+// Compact layout, neighbour phases (AA pull, A/B), row-segment waves with
+// buffer addressing.  The geometry of the wave is that of k_step_compact
+// (one 64-node row segment, the nine segment records), kept as lane masks:
+// for each row r around the segment, bit `lane` of wl / wm / wr is the fluid
+// flag of x - 1 / x / x + 1 in that row.  A population is read through the
+// descriptor of its direction pair {i, opp(i)} (the two arrays a lane
+// chooses between: the neighbour's slot in one, its own slot in the other),
+// at a 32-bit element offset picked per lane by the fluid mask of the
+// neighbour -- a select and an add per access, no branch and no 64-bit
+// address arithmetic.  In the AA pull the store of direction i goes exactly
+// where the load of opp(i) came from.  Needs 2 S (population stride) bytes
+// of storage element below 2^32 (checked on the host; k_step_compact serves
+// larger domains).
+template <int LAT, int OP, int PREC, int PAT, bool MON>
+__global__ __launch_bounds__(kMaxBlockThreads) void k_step_rows(const StepArgs a, const SegRec* __restrict__ recs)
+{
+    using L = Lattice<LAT>;
+    constexpr int Q = L::Q;
+    constexpr int D = L::D;
+    using S = typename Store<PREC>::S;
+    using C = typename Store<PREC>::C;
+    using T = typename Store<PREC>::T;
+    static_assert(PAT == PAT_AB || PAT == PAT_AA_PULL, "neighbour phases only");
+    constexpr int SH = sizeof(S) == 8 ? 3 : sizeof(S) == 4 ? 2 : 1;
+    // keep the 27 load offsets for the stores (reduced precision has the
+    // registers to spare) or rebuild them after the collision (FP64)
+    constexpr bool KEEP = sizeof(S) < 8;
+
+    const int b = blockIdx.x;
+    const int tile = (b & 7) * a.tiles_per_xcd + (b >> 3);
+    if (tile >= a.ntiles) return;  // whole block leaves together
+
+    const int lane = threadIdx.x & 63;
+    const int sx = a.tx >> 6;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int ly = (wv / sx) % a.ty;
+    const int lz = (wv / sx) / a.ty;
+    int ttx, tty, ttz;
+    tile_coords(a, tile, ttx, tty, ttz);
+    const int seg = ttx * sx + wv % sx;
+    const int x0 = seg * 64;
+    const int y = tty * a.ty + ly;
+    const int z = ttz * a.tz + lz;
+    const bool wave_in = (y < a.ny) && (z < a.nz) && (x0 < a.nx);
+    const int yc = min(y, a.ny - 1), zc = min(z, a.nz - 1), sc = min(seg, a.W - 1);
+    const uint64_t keep = wave_in ? ~0ull : 0ull;
+    const int lastbit = min(63, a.nx - 1 - x0);
+
+    uint64_t wl[9], wm[9], wr[9];
+    uint32_t im[9], rl[9], rr[9];
+#pragma unroll
+    for (int r = 0; r < 9; ++r) {
+        wl[r] = wm[r] = wr[r] = 0;
+        im[r] = rl[r] = rr[r] = 0;
+        if (D == 2 && r / 3 != 1) continue;
+        const SegRec* rp = recs + rec_row(yc + r % 3 - 1, zc + r / 3 - 1, a.ny) * a.W + sc;
+        wm[r] = rp->bits;
+        im[r] = rp->base;
+        rl[r] = rp->lidx;
+        rr[r] = rp->ridx;
+    }
+#pragma unroll
+    for (int r = 0; r < 9; ++r) {
+        if (D == 2 && r / 3 != 1) continue;
+        const uint64_t mb = wm[r] & keep;
+        const uint64_t lf = (wave_in && rl[r] != kNoSlot) ? 1ull : 0ull;
+        const uint64_t rf = (wave_in && rr[r] != kNoSlot) ? 1ull : 0ull;
+        wm[r] = uniform64(mb);
+        wl[r] = uniform64((mb << 1) | lf);
+        wr[r] = uniform64((mb >> 1) | (rf << lastbit));
+        im[r] += __builtin_amdgcn_mbcnt_hi((uint32_t)(mb >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mb, 0u));
+    }
+    const bool active = (wm[4] >> lane) & 1;
+    const uint32_t k = im[4];
+    const uint32_t St = (uint32_t)a.S;
+    const uint32_t pair_bytes = (uint32_t)(2 * a.S * (int64_t)sizeof(S));
+    const uint64_t not_first = ~1ull;
+    const uint64_t not_last = uniform64(~((1ull << 63) | (1ull << lastbit)));
+
+    // element offset, within the descriptor of pair {i, opp(i)}, of the
+    // population direction i pulls: the slot of x - c_i in array opp(i)
+    // (AA) / i (A/B) when that node is fluid, else the node's own slot in
+    // array i (AA) / opp(i) (A/B)
+    auto load_elem = [&](int i) -> uint32_t {
+        if (i == 0) return k;
+        const int o = opp(i), lo = i < o ? i : o;
+        const int r = (1 - L::cy[i]) + 3 * (1 - L::cz[i]);  // row of x - c_i
+        const int dx = -L::cx[i];
+        const int dn = PAT == PAT_AB ? i : o, db = PAT == PAT_AB ? o : i;
+        uint32_t nb;  // slot of x - c_i
+        if (dx == 0) nb = im[r];
+        else if (dx < 0) nb = lane_pick(not_first, im[r] - 1u, rl[r]);
+        else nb = lane_pick(not_last, lane_pick(wm[r], im[r] + 1u, im[r]), rr[r]);
+        const uint64_t fl = dx < 0 ? wl[r] : dx == 0 ? wm[r] : wr[r];
+        return lane_pick(fl, dn == lo ? nb : nb + St, db == lo ? k : k + St);
+    };
+
+    C h[Q];
+    uint32_t off[KEEP ? Q : 1];
+    C tau_prev = C(0);
+    const Coll<C>& cp = coll_of<C>(a);
+    Moments<C> mo;
+    Pre<C> pr;
+    bool used_fb = false;
+    if (active) {
+        const S* A = (const S*)a.src;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const int o = opp(i), lo = i < o ? i : o;
+            const uint32_t e = load_elem(i) << SH;
+            if constexpr (KEEP) off[i] = e;
+            h[i] = decode<PREC>(buf_ld<S>(pop_rsrc(A + (int64_t)lo * a.S, pair_bytes), e), L::w[i], a.h16_scale);
+        }
+        if constexpr (has_tau(OP)) tau_prev = (C)((const T*)a.tau)[k];
+
+        collide_node<LAT, OP, PREC>(h, tau_prev, a.fallback, a.cd, cp, mo, pr, used_fb);
+
+        if constexpr (PAT == PAT_AA_PULL && !KEEP) {
+            // rebuild the offsets from im instead of holding 27 through the
+            // collision; the empty asm hides im's history from the optimiser
+#pragma unroll
+            for (int r = 0; r < 9; ++r) asm volatile("" : "+v"(im[r]));
+        }
+        S* B = (S*)a.dst;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const S v = encode<PREC>(h[i], L::w[i], a.h16_inv);
+            if constexpr (PAT == PAT_AB) {
+                buf_st(v, pop_rsrc(B + (int64_t)i * a.S, pair_bytes / 2), k << SH);
+            } else {
+                const int o = opp(i), lo = i < o ? i : o;
+                const uint32_t e = KEEP ? off[o] : (load_elem(o) << SH);
+                buf_st(v, pop_rsrc(B + (int64_t)lo * a.S, pair_bytes), e);
+            }
+        }
+        if constexpr (has_tau(OP)) ((T*)a.tau)[k] = (T)pr.tau_p;
+    }
+    if constexpr (MON)
+        monitor_block<C>(active, mo, pr, cp, used_fb, a.partials + (int64_t)tile * MP_COUNT, a.uprev, k, a.S);
+}
+
 // Compact layout, AA local phase: every fluid node's streamed populations
 // already sit in its own slots, so this half of the AA pair needs no
 // geometry at all.  One thread per fluid slot, 256 slots per block: every
@@ -406,7 +599,7 @@ __global__ __launch_bounds__(256) void k_step_compact(const StepArgs a, const Se
 // (a cache-resident state would only lose its hits).  Monitor partials: one
 // per block.
 template <int LAT, int OP, int PREC, bool MON, bool NT>
-__global__ __launch_bounds__(256) void k_local_slots(const StepArgs a)
+__global__ __launch_bounds__(kMaxBlockThreads) void k_local_slots(const StepArgs a)
 {
     using L = Lattice<LAT>;
     constexpr int Q = L::Q;
@@ -477,7 +670,7 @@ __device__ __forceinline__ int select_bit(uint64_t v, uint32_t r)
 // x - 1 and x + 1 are the rank -1 / +1 neighbours except across the
 // periodic x boundary.  Blocks go to the XCDs as 8 contiguous slot ranges.
 template <int LAT, int OP, int PREC, int PAT, bool MON>
-__global__ __launch_bounds__(256) void k_pull_slots(const StepArgs a)
+__global__ __launch_bounds__(kMaxBlockThreads) void k_pull_slots(const StepArgs a)
 {
     using L = Lattice<LAT>;
     constexpr int Q = L::Q;
@@ -639,7 +832,12 @@ static hipError_t go_step(int layout, const StepArgs& a, hipStream_t s)
                                    0, s, a);
         }
     } else if (layout == LAYOUT_COMPACT) {
-        hipLaunchKernelGGL((k_step_compact<LAT, OP, PREC, PAT, MON>), grid, dim3(threads), 0, s, a, a.recs);
+        if constexpr (PAT != PAT_AA_LOCAL) {
+            if (a.buf_rows)
+                hipLaunchKernelGGL((k_step_rows<LAT, OP, PREC, PAT, MON>), grid, dim3(threads), 0, s, a, a.recs);
+            else
+                hipLaunchKernelGGL((k_step_compact<LAT, OP, PREC, PAT, MON>), grid, dim3(threads), 0, s, a, a.recs);
+        }
     } else {
         const int hz = (Lattice<LAT>::D == 3) ? a.tz + 2 : 1;
         const size_t sh = (PAT != PAT_AA_LOCAL) ? (size_t)(a.tx + 2) * (a.ty + 2) * hz : 0;

@@ -68,7 +68,7 @@ class lbm_sizes(ctypes.Structure):
 
 EXPORTS = ["lbm_last_error", "lbm_lattice_info", "lbm_query_sizes", "lbm_create", "lbm_bind",
            "lbm_set_mask", "lbm_init_equilibrium", "lbm_write_populations", "lbm_read_populations",
-           "lbm_step", "lbm_time", "lbm_set_monitor_interval", "lbm_read_history", "lbm_monitors",
+           "lbm_step", "lbm_set_graph_steps", "lbm_time", "lbm_set_monitor_interval", "lbm_read_history", "lbm_monitors",
            "lbm_set_umax_limit", "lbm_read_moments", "lbm_save", "lbm_load", "lbm_check_checkpoint", "lbm_set_tile",
            "lbm_get_tile", "lbm_set_tile_order", "lbm_get_tile_order", "lbm_set_pull_form", "lbm_get_pull_form",
            "lbm_autotune", "lbm_destroy",
@@ -112,6 +112,7 @@ def load_library(path: str = LIB_PATH):
         "lbm_write_populations": ([vp, dp, dp], ctypes.c_int),
         "lbm_read_populations": ([vp, dp, dp], ctypes.c_int),
         "lbm_step": ([vp, i64], ctypes.c_int),
+        "lbm_set_graph_steps": ([vp, i32], ctypes.c_int),
         "lbm_time": ([vp, ctypes.POINTER(i64)], ctypes.c_int),
         "lbm_set_monitor_interval": ([vp, i32], ctypes.c_int),
         "lbm_read_history": ([vp, ctypes.POINTER(lbm_monitor), i32, i32p], ctypes.c_int),
@@ -225,6 +226,10 @@ def lbm_read_populations(h, q, N, with_tau=False):
 
 def lbm_step(h, n):
     _check(load_library().lbm_step(h, int(n)))
+
+
+def lbm_set_graph_steps(h, steps):
+    _check(load_library().lbm_set_graph_steps(h, int(steps)))
 
 
 def lbm_time(h):
@@ -409,6 +414,9 @@ class Domain:
 
     def step(self, n=1):
         lbm_step(self.h, n)
+
+    def set_graph_steps(self, n):
+        lbm_set_graph_steps(self.h, n)
 
     @property
     def time(self):

@@ -83,9 +83,11 @@ def test_fp64_fallback_counts_and_matches(precision):
 
 @pytest.mark.parametrize("op", ["IR", "PR"])
 def test_full_size_bench_configuration(op):
-    """The bench workload at full size (D3Q27 256^3 sphere pack, FP64, AA,
-    compact, bench tile) from a seeded random state: two steps (both AA
-    phases) against two oracle steps, every fluid node compared."""
+    """The bench workload at full size (D3Q27 256^3 sphere pack, AA, compact,
+    bench tile) from a seeded random state: two steps (both AA phases)
+    against two oracle steps, every fluid node compared -- FP64 at the parity
+    bar, FP32 and FP16 with the FP64 redo (band 5% around the yield stress)
+    at their own bars."""
     from paper_1610_01388_amd import lbm
     n = 256
     mask, _ = inputs.sphere_pack((n, n, n), 8.0, 0.7, seed=1)
@@ -101,19 +103,25 @@ def test_full_size_bench_configuration(op):
     rho_o, u_o, _, uy_o = od.moments()
     od.close()
     perm = perm_lib_from_oracle(2)
-    dom = lbm.Domain("D3Q27", case["dims"], case["periodic"], op, case["nu_p"], case["sigma_y"], m=case["m"],
-                     g=case["g"], precision="FP64", scheme="AA", layout="COMPACT")
-    dom.set_mask(mask)
     P0 = P0[perm]
-    dom.write_populations(P0, tau0 if op == "PR" else None)
-    del P0
-    dom.step(2)
-    rho_g, u_g, _, uy_g = dom.moments()
-    dom.close()
     fluid = mask == 0
-    assert l2rel(u_g, u_o) <= 1e-10
-    assert np.max(np.abs(rho_g - rho_o)[fluid]) <= 1e-12
-    assert np.array_equal(uy_g, uy_o)
+    for precision, kw in (("FP64", {}), ("FP32", {}),
+                          ("FP16", dict(fp64_fallback=True, fallback_band=0.05, fp16_scale_log2=14))):
+        dom = lbm.Domain("D3Q27", case["dims"], case["periodic"], op, case["nu_p"], case["sigma_y"], m=case["m"],
+                         g=case["g"], precision=precision, scheme="AA", layout="COMPACT", **kw)
+        dom.set_mask(mask)
+        dom.write_populations(P0, tau0 if op == "PR" else None)
+        dom.step(2)
+        rho_g, u_g, _, uy_g = dom.moments()
+        dom.close()
+        print(f"{op} {precision} 256^3: u L2-rel {l2rel(u_g, u_o):.2e}", flush=True)
+        if precision == "FP64":
+            assert l2rel(u_g, u_o) <= 1e-10
+            assert np.max(np.abs(rho_g - rho_o)[fluid]) <= 1e-12
+            assert np.array_equal(uy_g, uy_o)
+        else:
+            assert l2rel(u_g, u_o) <= PREC_TOL[precision]["u"]
+            assert np.max(np.abs(rho_g - rho_o)[fluid]) <= PREC_TOL[precision]["rho"]
 
 
 def test_d3q19_duct_config_vs_oracle():
@@ -170,6 +178,47 @@ def test_fused_monitors_match_oracle_and_on_demand():
     r = od.residual(uprev, record=False)  # on demand: against the step-30 record, nothing stored
     assert abs(now["residual"] - r["residual"]) <= 1e-9 * r["residual"]
     assert dom.monitors()["residual"] == now["residual"]
+
+
+@pytest.mark.parametrize("op", ["IR", "PR"])
+@pytest.mark.parametrize("solid,form", [(0.2, "ROWS"), (0.85, "SLOTS")])
+def test_fused_monitor_records_at_odd_times(op, solid, form):
+    """Fused records every 3 steps: the even-time ones come from the AA
+    neighbour phase (row-segment kernel on a 20%-solid grid, slot kernel on an
+    85%-solid one), the odd-time ones from the AA local phase (one block per
+    256 slots); every record against the oracle's monitors and residual."""
+    from paper_1610_01388_amd import lbm
+    lat, dims, per = 2, (70, 13, 9), (1, 0, 1)
+    N = int(np.prod(dims))
+    mask = random_mask(N, 19 if form == "ROWS" else 23, solid)
+    g = (2e-5, -1e-5, 5e-6)
+    sy = 2e-4
+    rh = oracle.rheology(oracle.IR if op == "IR" else oracle.PR, 0.1, sy, 1e4, 1e-8, 0.25, g)
+    od = oracle.Domain(lat, dims, per, rh, mask)
+    P0, tau0 = random_state(lat, N, 29)
+    P0 = P0 * (1 - mask)[None, :]
+    od.set_state(P0, tau0)
+    dom = lbm.Domain("D3Q27", dims, per, op, 0.1, sy, m=1e4, g=g)
+    dom.set_mask(mask)
+    dom.set_pull_form(form)
+    assert dom.pull_form() == form
+    dom.write_populations(P0[perm_lib_from_oracle(lat)], tau0 if op == "PR" else None)
+    dom.set_monitor_interval(3)
+    dom.step(14)
+    hist = dom.history()
+    assert [h["step"] for h in hist] == [0, 3, 6, 9, 12]
+    uprev = np.zeros(3 * N)
+    for h in hist:
+        od.step(h["step"] - od.time)
+        om = od.monitors()
+        r = od.residual(uprev)
+        assert h["fluid"] == om["fluid"] and h["unyielded"] == om["unyielded"] and h["nonfinite"] == 0
+        for a in range(3):
+            assert abs(h["flux"][a] - om["flux"][a]) <= 1e-12 * max(abs(om["flux"][a]), 1e-30), (h["step"], a)
+        assert abs(h["mass"] - om["mass"]) <= 1e-10
+        assert abs(h["umax"] - om["umax"]) <= 1e-12 * om["umax"]
+        assert abs(h["residual"] - r["residual"]) <= 1e-9 * r["residual"]
+        assert abs(h["du_max"] - r["du_max"]) <= 1e-9 * r["du_max"]
 
 
 @pytest.mark.parametrize("layout", ["COMPACT", "DENSE"])
