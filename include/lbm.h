@@ -241,6 +241,21 @@ int lbm_read_history(lbm_domain* dom, lbm_monitor* out, int32_t max, int32_t* co
  * by lbm_set_umax_limit (default 0.1, the Mach validity bound of Sec. 4.5.3). */
 int lbm_monitors(lbm_domain* dom, lbm_monitor* out);
 int lbm_set_umax_limit(lbm_domain* dom, double umax);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * monitors of the current state, as lbm_monitors computes them (residual
+ * against the last fused record, nothing stored), written as one lbm_monitor
+ * into caller-owned device memory record_dev (8-byte aligned), enqueued on
+ * the bound stream without synchronising.  Its kernels keep their per-block
+ * partial sums in a per-GPU file-scope device array of 2048 x 12 doubles
+ * (192 KiB, held by each GPU the library runs on until the process ends), not
+ * in the bound work buffer; the reduction runs at most 2048 blocks (a grid
+ * stride over the nodes), so every domain size fits.  Nothing is allocated,
+ * freed or cleared: every block overwrites its own partials.  Calls that
+ * overlap on one GPU (other streams or threads) race on that array and must
+ * be serialised by the caller.  No LBM_EUNSTABLE check: the record carries
+ * nonfinite and umax.  LBM_EINVAL for a NULL or misaligned record_dev. */
+int lbm_monitors_async(lbm_domain* dom, void* record_dev);
 
 /* Moments of the current state into host buffers (N doubles rho, 3*N
  * doubles u component-major u[a*N+n], N doubles nu_app (PR; IR reports

@@ -763,6 +763,27 @@ int lbm_monitors(lbm_domain* dm, lbm_monitor* out)
     return LBM_OK;
 }
 
+int lbm_monitors_async(lbm_domain* dm, void* record_dev)
+{
+    int rc = need_bound(dm);
+    if (rc) return rc;
+    if (!record_dev || (uintptr_t)record_dev % 8) return fail(LBM_EINVAL, "record_dev must be 8-byte aligned device memory");
+    double* parts = nullptr;
+    HIPCHK(scratch_partials(dm->stream, &parts));
+    NodeArgs a = node_args(dm);
+    a.n0 = 0;
+    a.count = dm->N;
+    a.reduce = 1;
+    a.partials = parts;
+    int64_t nb = 0;
+    HIPCHK(launch_readout(dm->d.lattice, kernel_op(dm->r), dm->d.precision, a, dm->stream, &nb, kScratchBlocks));
+    if (nb > kScratchBlocks)
+        return fail(LBM_EINVAL, "monitor reduction needs %lld partial blocks, the scratch holds %lld", (long long)nb,
+                    (long long)kScratchBlocks);
+    HIPCHK(launch_finalize(parts, nb, record_dev, dm->t, (double)dm->N, dm->stream));
+    return LBM_OK;
+}
+
 int lbm_set_umax_limit(lbm_domain* dm, double umax)
 {
     if (!dm) return fail(LBM_EINVAL, "domain is NULL");

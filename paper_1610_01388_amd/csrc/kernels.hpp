@@ -170,4 +170,9 @@ hipError_t launch_pop_write(int lat, int prec, const NodeArgs& a, hipStream_t s)
 hipError_t launch_pop_read(int lat, int prec, const NodeArgs& a, hipStream_t s);
 hipError_t launch_fill_u8(uint8_t* p, int64_t n, uint8_t v, hipStream_t s);
 
+// Allocation-free monitors: blocks of partial sums the per-GPU scratch array
+// holds, and its device address on the device of stream s.
+constexpr int64_t kScratchBlocks = 2048;
+hipError_t scratch_partials(hipStream_t s, double** out);
+
 }  // namespace lbm

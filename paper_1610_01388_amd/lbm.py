@@ -69,7 +69,7 @@ class lbm_sizes(ctypes.Structure):
 EXPORTS = ["lbm_last_error", "lbm_lattice_info", "lbm_query_sizes", "lbm_create", "lbm_bind",
            "lbm_set_mask", "lbm_init_equilibrium", "lbm_write_populations", "lbm_read_populations",
            "lbm_step", "lbm_set_graph_steps", "lbm_time", "lbm_set_monitor_interval", "lbm_read_history", "lbm_monitors",
-           "lbm_set_umax_limit", "lbm_read_moments", "lbm_save", "lbm_load", "lbm_check_checkpoint", "lbm_set_tile",
+           "lbm_set_umax_limit", "lbm_monitors_async", "lbm_read_moments", "lbm_save", "lbm_load", "lbm_check_checkpoint", "lbm_set_tile",
            "lbm_get_tile", "lbm_set_tile_order", "lbm_get_tile_order", "lbm_set_pull_form", "lbm_get_pull_form",
            "lbm_autotune", "lbm_destroy",
            "lbm_batch_query_sizes", "lbm_batch_create", "lbm_batch_bind", "lbm_batch_init_equilibrium",
@@ -118,6 +118,7 @@ def load_library(path: str = LIB_PATH):
         "lbm_read_history": ([vp, ctypes.POINTER(lbm_monitor), i32, i32p], ctypes.c_int),
         "lbm_monitors": ([vp, ctypes.POINTER(lbm_monitor)], ctypes.c_int),
         "lbm_set_umax_limit": ([vp, ctypes.c_double], ctypes.c_int),
+        "lbm_monitors_async": ([vp, vp], ctypes.c_int),
         "lbm_read_moments": ([vp, dp, dp, dp, u8p], ctypes.c_int),
         "lbm_save": ([vp, vp, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
         "lbm_load": ([vp, vp, ctypes.c_size_t], ctypes.c_int),
@@ -257,6 +258,12 @@ def lbm_monitors(h, raise_unstable=True):
     d = m.as_dict()
     d["status"] = rc
     return d
+
+
+def lbm_monitors_async(h, record_dev_ptr: int):
+    """Enqueue the allocation-free monitors into device memory at
+    record_dev_ptr (one lbm_monitor, 96 bytes); no synchronisation."""
+    _check(load_library().lbm_monitors_async(h, ctypes.c_void_p(int(record_dev_ptr))))
 
 
 def lbm_set_umax_limit(h, umax):
