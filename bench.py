@@ -106,12 +106,15 @@ def compare(ref, got, axis):
             "unyielded_ref": pr, "unyielded": pg}
 
 
-def run_form(torch, lbm, name, case, precision, mask, fluid, warmup, steps, ref=None, develop=0, **kw):
+def run_form(torch, lbm, name, case, precision, mask, fluid, warmup, steps, ref=None, develop=0, graph=0, **kw):
     """One bench form: from rest, `develop` untimed steps, the moments at that
     time (the accuracy snapshot, compared with `ref` when given), then
     `warmup` untimed and `steps` timed steps.  The snapshot horizon does not
-    depend on the timed step count."""
+    depend on the timed step count.  graph > 0: steps replayed from captured
+    graphs of that many launches."""
     dom = make_domain(lbm, case, precision, mask=mask, **kw)
+    if graph:
+        dom.set_graph_steps(graph)
     mom = None
     if develop:
         dom.step(develop)
@@ -121,7 +124,7 @@ def run_form(torch, lbm, name, case, precision, mask, fluid, warmup, steps, ref=
     bpn = algorithmic_bytes_per_node(case["lattice"], case["op"], precision)
     gbs = fluid * bpn * steps / (ms * 1e-3) / 1e9
     out = {"form": name, "lattice": case["lattice"], "operator": case["op"], "precision": precision,
-           "dims": list(case["dims"]), "fluid_nodes": int(fluid), "steps": steps,
+           "dims": list(case["dims"]), "fluid_nodes": int(fluid), "steps": steps, "graph_steps": graph,
            "ms_per_step": ms / steps, "MLUPS": mlups, "algorithmic_GBs": gbs,
            "hbm_frac": gbs / HBM_PEAK_GBS, "bytes_per_node": bpn}
     if kw.get("fp64_fallback"):
@@ -357,8 +360,9 @@ def oracle_threads():
     return max(1, n)
 
 
-def time_oracle(case, mask, steps, threads):
-    """MLUPS of the FP64 oracle (as it stands) on `steps` steps of a case."""
+def time_oracle(case, mask, steps, threads, chunk=None):
+    """MLUPS of the FP64 oracle (as it stands) on `steps` steps of a case
+    (stepped in chunks with a progress line each, when given)."""
     import oracle
     op = {"PR": oracle.PR, "IR": oracle.IR, "PRI": oracle.PRI}[case["op"]]
     lat = {"D2Q9": 0, "D3Q19": 1, "D3Q27": 2}[case["lattice"]]
@@ -367,7 +371,14 @@ def time_oracle(case, mask, steps, threads):
     od = oracle.Domain(lat, case["dims"], case["periodic"], rh, mask)
     fluid = int(np.prod(case["dims"])) if mask is None else int((np.asarray(mask) == 0).sum())
     t0 = time.perf_counter()
-    od.step(steps)
+    done = 0
+    while done < steps:
+        n = min(steps - done, chunk or steps)
+        od.step(n)
+        done += n
+        if chunk:
+            log(f"  oracle {case['lattice']} {case['op']}: {done}/{steps} steps on {used} threads, "
+                f"{time.perf_counter() - t0:.1f} s")
     dt = time.perf_counter() - t0
     od.close()
     return fluid * steps / dt / 1e6, dt, used
@@ -404,8 +415,8 @@ def cpu_configs(inputs):
                           "MLUPS_1_thread": one, "seconds_1_thread": dt1, "MLUPS_all": allc, "seconds_all": dtn,
                           "threads": used, "host": host}), flush=True)
     duct = inputs.duct_case("IR", side=128, length=4, Bi=0.5)
-    allc, dtn, used = time_oracle(duct, None, 50000, nthr)
-    one, dt1, _ = time_oracle(duct, None, 1000, 1)
+    allc, dtn, used = time_oracle(duct, None, 50000, nthr, chunk=2500)
+    one, dt1, _ = time_oracle(duct, None, 1000, 1, chunk=250)
     print(json.dumps({"cpu_config": "D3Q19 4x128x128 square duct, Bi 0.5, IR", "MLUPS_all_50000_steps": allc,
                       "seconds_all": dtn, "threads": used, "MLUPS_1_thread_1000_steps": one, "seconds_1_thread": dt1,
                       "host": host}), flush=True)
@@ -537,7 +548,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "algorithmic_bytes_per_launch": per_launch, "bytes_per_fluid_node": bpn,
-                     "kernel": (("k_step_compact" if nk == "ROWS" else "k_pull_slots")
+                     "kernel": (("k_step_rows" if nk == "ROWS" else "k_pull_slots")
                                 + "<D3Q27, IR, FP64, AA pull> and k_local_slots<D3Q27, IR, FP64> "
                                 "(AA local)" if args.layout == "COMPACT" else "k_step<D3Q27, IR, FP64, AA pull/local>")
                                + ", mean of the two alternating AA phases",
@@ -625,12 +636,21 @@ def main():
             del ref4
         del mask4
     if "duct" in groups:
-        log("forms: D3Q19 4x128x128 duct (cache-resident: MLUPS only)")
+        # small and cache-resident: MLUPS only; launch-bound, so each precision
+        # is timed with eager launches and with replays of 100-step graphs
+        # (1000 steps to develop, 100 warmup, 500 timed: whole replays,
+        # whatever --steps is)
+        log("forms: D3Q19 4x128x128 duct, eager launches and 100-step graph replays")
         duct = inputs.duct_case("IR", side=128, length=4, Bi=0.5)
         dfl = 128 * 128 * 4
-        d64, dref = run_form(torch, lbm, "duct D3Q19 IR FP64", duct, "FP64", None, dfl, W, K, develop=H)
-        d32, _ = run_form(torch, lbm, "duct D3Q19 IR FP32", duct, "FP32", None, dfl, W, K, ref=dref, develop=H)
-        forms += [d64, d32]
+        d64, dref = run_form(torch, lbm, "duct D3Q19 IR FP64", duct, "FP64", None, dfl, 100, 500, develop=1000)
+        g64, _ = run_form(torch, lbm, "duct D3Q19 IR FP64, 100-step graphs", duct, "FP64", None, dfl, 100, 500,
+                          ref=dref, develop=1000, graph=100)
+        d32, _ = run_form(torch, lbm, "duct D3Q19 IR FP32", duct, "FP32", None, dfl, 100, 500, ref=dref,
+                          develop=1000)
+        g32, _ = run_form(torch, lbm, "duct D3Q19 IR FP32, 100-step graphs", duct, "FP32", None, dfl, 100, 500,
+                          ref=dref, develop=1000, graph=100)
+        forms += [d64, g64, d32, g32]
     if "batch" in groups:
         log("forms: batched sweep, 256 D3Q19 ducts (sides 32..160, length 4), FP32 vs FP64, 1000-step graph")
         forms.append(batch_form(torch, lbm, inputs.batch_sweep(), 1000, 1000))
