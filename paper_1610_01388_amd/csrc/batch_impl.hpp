@@ -51,9 +51,9 @@ __device__ __forceinline__ void batch_tile(const BatchArgs& a, const BatchSim& s
         z = ttz * sm.tz + lz;
     }
     const bool active = (x < sm.nx) & (y < sm.ny) & (z < sm.nz);
-    // indices inside one simulation fit 32 bits (Q * N < 2^31 is checked on
-    // the host)
-    const int N = (int)sm.N;
+    // indices inside one simulation fit 32 bits (Q * S < 2^31 is checked on
+    // the host); S is the direction stride
+    const int St = (int)sm.S;
     const int n = x + sm.nx * (y + sm.ny * z);
     const Coll<C>& cp = [&]() -> const Coll<C>& {
         if constexpr (PREC == PREC_F64) return sm.cd;
@@ -87,9 +87,9 @@ __device__ __forceinline__ void batch_tile(const BatchArgs& a, const BatchSim& s
             int idx;
             const int s = nb(-L::cx[i], -L::cy[i], -L::cz[i]);
             if constexpr (PAT == PAT_AB)
-                idx = s >= 0 ? i * N + s : opp(i) * N + n;
+                idx = s >= 0 ? i * St + s : opp(i) * St + n;
             else
-                idx = s >= 0 ? opp(i) * N + s : i * N + n;
+                idx = s >= 0 ? opp(i) * St + s : i * St + n;
             h[i] = decode<PREC>(A[idx], L::w[i], a.h16_scale);
         }
         T* tau = (T*)a.tau + sm.off_tau;
@@ -103,10 +103,10 @@ __device__ __forceinline__ void batch_tile(const BatchArgs& a, const BatchSim& s
         for (int i = 0; i < Q; ++i) {
             int idx;
             if constexpr (PAT == PAT_AB) {
-                idx = i * N + n;  // A/B is not offered for batches; kept for completeness
+                idx = i * St + n;  // A/B is not offered for batches; kept for completeness
             } else {
                 const int d = nb(L::cx[i], L::cy[i], L::cz[i]);
-                idx = d >= 0 ? i * N + d : opp(i) * N + n;
+                idx = d >= 0 ? i * St + d : opp(i) * St + n;
             }
             B[idx] = encode<PREC>(h[i], L::w[i], a.h16_inv);
         }
@@ -114,7 +114,7 @@ __device__ __forceinline__ void batch_tile(const BatchArgs& a, const BatchSim& s
     }
     if constexpr (MON)
         monitor_block<C>(active, mo, pr, cp, used_fb, a.partials + (int64_t)item * MP_COUNT,
-                         a.uprev ? a.uprev + sm.off_u : nullptr, n, N);
+                         a.uprev ? a.uprev + sm.off_u : nullptr, n, St);
 }
 
 // AA local phase of one item.  This half of the AA pair touches only the
@@ -131,9 +131,9 @@ __device__ __forceinline__ void batch_local(const BatchArgs& a, const BatchSim& 
     using C = typename Store<PREC>::C;
     using T = typename Store<PREC>::T;
 
-    const int N = (int)sm.N;  // Q * N < 2^31 is checked on the host
+    const int St = (int)sm.S;  // direction stride; Q * S < 2^31 is checked on the host
     const int n = (item - sm.item0) * 256 + (int)threadIdx.x;
-    const bool active = n < N;
+    const bool active = n < (int)sm.N;
     const Coll<C>& cp = [&]() -> const Coll<C>& {
         if constexpr (PREC == PREC_F64) return sm.cd;
         else return sm.cf;
@@ -146,7 +146,7 @@ __device__ __forceinline__ void batch_local(const BatchArgs& a, const BatchSim& 
         const S* A = (const S*)a.pdf + sm.off_pdf;
         C h[Q];
 #pragma unroll
-        for (int i = 0; i < Q; ++i) h[i] = decode<PREC>(A[i * N + n], L::w[i], a.h16_scale);
+        for (int i = 0; i < Q; ++i) h[i] = decode<PREC>(A[i * St + n], L::w[i], a.h16_scale);
         T* tau = (T*)a.tau + sm.off_tau;
         C tau_prev = C(0);
         if constexpr (has_tau(OP)) tau_prev = (C)tau[n];
@@ -155,12 +155,12 @@ __device__ __forceinline__ void batch_local(const BatchArgs& a, const BatchSim& 
 
         S* B = (S*)a.pdf + sm.off_pdf;
 #pragma unroll
-        for (int i = 0; i < Q; ++i) B[opp(i) * N + n] = encode<PREC>(h[i], L::w[i], a.h16_inv);
+        for (int i = 0; i < Q; ++i) B[opp(i) * St + n] = encode<PREC>(h[i], L::w[i], a.h16_inv);
         if constexpr (has_tau(OP)) tau[n] = (T)pr.tau_p;
     }
     if constexpr (MON)
         monitor_block<C>(active, mo, pr, cp, used_fb, a.partials + (int64_t)item * MP_COUNT,
-                         a.uprev ? a.uprev + sm.off_u : nullptr, n, N);
+                         a.uprev ? a.uprev + sm.off_u : nullptr, n, St);
 }
 
 // Work-item order.  xcd_chunks == 0: block b takes items b, b + G, ...

@@ -1157,12 +1157,13 @@ int batch_plan(lbm_batch* b)
         s.nitems = (int)items;
         for (int64_t j = 0; j < items; ++j) b->work.push_back(k);
         s.N = (int64_t)d.nx * d.ny * d.nz;
+        s.S = (s.N + 63) / 64 * 64;
         s.off_pdf = off_pdf;
         s.off_tau = off_tau;
         s.off_u = off_u;
-        off_pdf += (s.N * b->Q + 63) / 64 * 64;
-        off_tau += (s.N + 63) / 64 * 64;
-        off_u += 3 * ((s.N + 63) / 64 * 64);
+        off_pdf += s.S * b->Q;
+        off_tau += s.S;
+        off_u += 3 * s.S;
         s.cd = make_coll<double>(b->r[k]);
         s.cf = make_coll<float>(b->r[k]);
     }
@@ -1295,7 +1296,7 @@ NodeArgs batch_node_args(lbm_batch* b, int k)
     a.partials = (double*)(b->workbuf + b->L.parts);
     a.uprev = (const double*)(b->workbuf + b->L.uprev) + s.off_u;
     a.N = s.N;
-    a.S = s.N;
+    a.S = s.S;
     a.nx = s.nx; a.ny = s.ny; a.nz = s.nz;
     for (int q = 0; q < 3; ++q) a.per[q] = s.per[q];
     a.layout = b->parity == 0 ? 1 : 2;
@@ -1329,7 +1330,8 @@ int batch_validate(const lbm_desc* descs, const lbm_rheology* rh, int32_t count)
             return fail(LBM_EINVAL, "simulation %d: batches take the PR and IR operators", k);
         if (rh[k].mrt_bulk > 0 || rh[k].mrt_even > 0)
             return fail(LBM_EINVAL, "simulation %d: batches use the TRT base collision (no MRT rates)", k);
-        if ((int64_t)descs[k].nx * descs[k].ny * descs[k].nz * lattice_q(descs[k].lattice) >= ((int64_t)1 << 31))
+        if (((int64_t)descs[k].nx * descs[k].ny * descs[k].nz + 63) / 64 * 64 * lattice_q(descs[k].lattice) >=
+            ((int64_t)1 << 31))
             return fail(LBM_EINVAL, "simulation %d: batched simulations need Q * nodes < 2^31", k);
         if (rh[k].fp64_fallback != rh[0].fp64_fallback || rh[k].fp16_scale_log2 != rh[0].fp16_scale_log2)
             return fail(LBM_EINVAL, "all simulations of a batch share the fallback flag and the FP16 scale");
@@ -1432,7 +1434,7 @@ int lbm_batch_write_populations(lbm_batch* b, int32_t sim, const double* host_P,
     if (b->parity != 0) return fail(LBM_ESTATE, "write populations only between step pairs (even time)");
     const BatchSim& s = b->sims[sim];
     HIPCHK(hipMemsetAsync(b->workbuf + b->L.uprev + (size_t)s.off_u * sizeof(double), 0,
-                          (size_t)3 * s.N * sizeof(double), b->stream));
+                          (size_t)3 * s.S * sizeof(double), b->stream));
     const int Q = b->Q;
     const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(s.N, (int64_t)((b->L.total - b->L.stage) / ((Q + 1) * 8))));
     double* stage = (double*)(b->workbuf + b->L.stage);

@@ -128,9 +128,11 @@ struct BatchSim {
     int item0, nitems;     // this simulation's work items [item0, item0 + nitems)
     int linear;            // 1: items are runs of 256 consecutive nodes (rows wrap) instead of tiles
     int64_t N;             // nodes
-    int64_t off_pdf;       // element offset of the simulation's population block ([i][n], stride N)
+    int64_t S;             // direction stride: N rounded up to a multiple of 64, so that every
+                           // direction's array starts on a cache-line boundary
+    int64_t off_pdf;       // element offset of the simulation's population block ([i][n], stride S)
     int64_t off_tau;       // element offset of its relaxation-time block (PR)
-    int64_t off_u;         // element offset of its previous-velocity block ([3][N] doubles)
+    int64_t off_u;         // element offset of its previous-velocity block ([3][S] doubles)
     Coll<double> cd;
     Coll<float> cf;
 };
