@@ -92,6 +92,28 @@ def timed_run(torch, dom, warmup, steps, mon_every=100):
     return ms, wall
 
 
+def device_copy_rate(torch, nbytes=2 << 30, reps=10):
+    """Read + write bytes per second of a plain device-to-device copy of
+    nbytes (torch's copy kernel): what a streaming kernel reaches on this
+    GPU, the practical ceiling beside the published peak."""
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1)
+    for _ in range(2):
+        b.copy_(a)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * nbytes * reps / (ms * 1e-3) / 1e9
+
+
 def compare(ref, got, axis):
     """Velocity L2-rel, flux rel (along the force axis), plug volume
     (unyielded count) rel."""
@@ -489,13 +511,6 @@ def main():
         darcy_sweep(torch, lbm, inputs, args.size, (0.1, 0.316, 1.0, 3.16, 10.0), ("IR", "PR"), args.darcy_cap)
         return
 
-    if args.batch_only:
-        log(f"batched sweep only: warmup {args.warmup}, steps {args.steps}")
-        g = 1000 if args.steps % 1000 == 0 and args.warmup % 1000 == 0 else 100
-        print(json.dumps(batch_form(torch, lbm, inputs.batch_sweep(), args.warmup, args.steps, graph_steps=g)),
-              flush=True)
-        return
-
     if args.copy_calibration:
         a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
         b = torch.empty_like(a)
@@ -505,6 +520,13 @@ def main():
         torch.cuda.synchronize()
         del a, b
         torch.cuda.empty_cache()
+
+    if args.batch_only:
+        log(f"batched sweep only: warmup {args.warmup}, steps {args.steps}")
+        g = 1000 if args.steps % 1000 == 0 and args.warmup % 1000 == 0 else 100
+        print(json.dumps(batch_form(torch, lbm, inputs.batch_sweep(), args.warmup, args.steps, graph_steps=g)),
+              flush=True)
+        return
 
     n = args.size
     log(f"generating {n}^3 sphere pack (R=8, porosity 0.7, seed 1)")
@@ -530,6 +552,8 @@ def main():
     achieved = per_launch / (ms_step * 1e-3) / 1e9
     khash = kernel_source_hash()
     traffic = traffic_from_profile(khash, per_launch) if args.layout == "COMPACT" else None
+    copy_gbs = device_copy_rate(torch)
+    log(f"  device copy (2 GiB, read + write): {copy_gbs:.0f} GB/s")
     log(f"  {ms_step:.3f} ms/step, {mlups:.1f} MLUPS, {achieved:.0f} GB/s algorithmic")
 
     result = {
@@ -552,7 +576,8 @@ def main():
                                 + "<D3Q27, IR, FP64, AA pull> and k_local_slots<D3Q27, IR, FP64> "
                                 "(AA local)" if args.layout == "COMPACT" else "k_step<D3Q27, IR, FP64, AA pull/local>")
                                + ", mean of the two alternating AA phases",
-                     "kernel_source_hash": khash},
+                     "kernel_source_hash": khash,
+                     "device_copy_GBs": copy_gbs, "frac_of_device_copy": achieved / copy_gbs},
     }
     if hist:
         result["config"]["last_monitor"] = {"step": hist[-1]["step"], "flux": float(hist[-1]["flux"][0]),
