@@ -250,7 +250,9 @@ int lbm_set_umax_limit(lbm_domain* dom, double umax);
  * partial sums in a per-GPU file-scope device array of 2048 x 12 doubles
  * (192 KiB, held by each GPU the library runs on until the process ends), not
  * in the bound work buffer; the reduction runs at most 2048 blocks (a grid
- * stride over the nodes), so every domain size fits.  Nothing is allocated,
+ * stride over the nodes), so every domain size fits.  lbm_bind resolves the
+ * array's address on the bound stream's GPU, so this call does no symbol
+ * lookup: it enqueues two kernels.  Nothing is allocated,
  * freed or cleared: every block overwrites its own partials.  Calls that
  * overlap on one GPU (other streams or threads) race on that array and must
  * be serialised by the caller.  No LBM_EUNSTABLE check: the record carries

@@ -152,6 +152,7 @@ struct lbm_domain {
     hipStream_t cap = nullptr;
     uint64_t gen = 0;        // bumped by every change to what the step launches bake in
     uint64_t graph_gen = 0;  // gen the graph was captured at
+    double* scratch = nullptr;  // this GPU's allocation-free monitor scratch (resolved by lbm_bind)
 };
 
 namespace {
@@ -578,6 +579,10 @@ int lbm_bind(lbm_domain* dm, void* pdf_dev, void* tau_dev, void* mask_dev, void*
     dm->mask = (uint8_t*)mask_dev;
     dm->work = (char*)work_dev;
     dm->stream = (hipStream_t)hip_stream;
+    // resolve this GPU's allocation-free monitor scratch now, at set-up, so
+    // that lbm_monitors_async looks nothing up when it runs (e.g. under
+    // graph capture)
+    HIPCHK(scratch_partials(dm->stream, &dm->scratch));
     dm->bound = true;
     int rc = upload_mask(dm, nullptr);
     if (rc) return rc;
@@ -768,18 +773,17 @@ int lbm_monitors_async(lbm_domain* dm, void* record_dev)
     int rc = need_bound(dm);
     if (rc) return rc;
     if (!record_dev || (uintptr_t)record_dev % 8) return fail(LBM_EINVAL, "record_dev must be 8-byte aligned device memory");
-    double* parts = nullptr;
-    HIPCHK(scratch_partials(dm->stream, &parts));
+    double* parts = dm->scratch;
+    if (!parts) return fail(LBM_ESTATE, "no monitor scratch resolved for the bound stream");
     NodeArgs a = node_args(dm);
     a.n0 = 0;
     a.count = dm->N;
     a.reduce = 1;
     a.partials = parts;
+    // at most kScratchBlocks blocks: larger domains are walked with a grid
+    // stride, so the scratch always holds every block's partials
     int64_t nb = 0;
     HIPCHK(launch_readout(dm->d.lattice, kernel_op(dm->r), dm->d.precision, a, dm->stream, &nb, kScratchBlocks));
-    if (nb > kScratchBlocks)
-        return fail(LBM_EINVAL, "monitor reduction needs %lld partial blocks, the scratch holds %lld", (long long)nb,
-                    (long long)kScratchBlocks);
     HIPCHK(launch_finalize(parts, nb, record_dev, dm->t, (double)dm->N, dm->stream));
     return LBM_OK;
 }
