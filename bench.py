@@ -114,6 +114,26 @@ def device_copy_rate(torch, nbytes=2 << 30, reps=10):
     return 2 * nbytes * reps / (ms * 1e-3) / 1e9
 
 
+def phase_times(torch, dom, pairs=20):
+    """Mean duration of each AA phase, timed one launch at a time with HIP
+    events on the domain's stream (monitors off; the state just advances):
+    the pull (neighbour) phase at even times, the local phase at odd ones."""
+    dom.set_monitor_interval(0)
+    if dom.time % 2:
+        dom.step(1)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3 * pairs)]
+    for p in range(pairs):
+        ev[3 * p].record(dom.stream)
+        dom.step(1)
+        ev[3 * p + 1].record(dom.stream)
+        dom.step(1)
+        ev[3 * p + 2].record(dom.stream)
+    torch.cuda.synchronize()
+    pull = [ev[3 * p].elapsed_time(ev[3 * p + 1]) for p in range(pairs)]
+    loc = [ev[3 * p + 1].elapsed_time(ev[3 * p + 2]) for p in range(pairs)]
+    return {"pull_ms": float(np.mean(pull)), "local_ms": float(np.mean(loc))}
+
+
 def compare(ref, got, axis):
     """Velocity L2-rel, flux rel (along the force axis), plug volume
     (unyielded count) rel."""
@@ -543,6 +563,7 @@ def main():
     nk = dom.pull_form() if args.layout == "COMPACT" else None
     ms, wall = timed_run(torch, dom, args.warmup, args.steps)
     hist = dom.history()
+    phases = phase_times(torch, dom) if args.layout == "COMPACT" else None
     dom.close()
     torch.cuda.empty_cache()
     ms_step = ms / args.steps
@@ -579,6 +600,13 @@ def main():
                      "kernel_source_hash": khash,
                      "device_copy_GBs": copy_gbs, "frac_of_device_copy": achieved / copy_gbs},
     }
+    if phases:
+        # each AA phase moves the same algorithmic bytes; the pull phase is the slower kernel
+        result["roofline"]["phases"] = {
+            "pull_ms": phases["pull_ms"], "local_ms": phases["local_ms"],
+            "pull_frac": per_launch / (phases["pull_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "local_frac": per_launch / (phases["local_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "method": "HIP events around single launches on the domain's stream, 20 pairs after the timed steps"}
     if hist:
         result["config"]["last_monitor"] = {"step": hist[-1]["step"], "flux": float(hist[-1]["flux"][0]),
                                             "mass": hist[-1]["mass"], "umax": hist[-1]["umax"],
