@@ -86,8 +86,8 @@ def test_full_size_bench_configuration(op):
     """The bench workload at full size (D3Q27 256^3 sphere pack, AA, compact,
     bench tile) from a seeded random state: two steps (both AA phases)
     against two oracle steps, every fluid node compared -- FP64 at the parity
-    bar, FP32 and FP16 with the FP64 redo (band 5% around the yield stress)
-    at their own bars."""
+    bar, FP32, FP16 and FP16 with the FP64 redo (band 5% around the yield
+    stress) at their own bars."""
     from paper_1610_01388_amd import lbm
     n = 256
     mask, _ = inputs.sphere_pack((n, n, n), 8.0, 0.7, seed=1)
@@ -105,7 +105,7 @@ def test_full_size_bench_configuration(op):
     perm = perm_lib_from_oracle(2)
     P0 = P0[perm]
     fluid = mask == 0
-    for precision, kw in (("FP64", {}), ("FP32", {}),
+    for precision, kw in (("FP64", {}), ("FP32", {}), ("FP16", dict(fp16_scale_log2=14)),
                           ("FP16", dict(fp64_fallback=True, fallback_band=0.05, fp16_scale_log2=14))):
         dom = lbm.Domain("D3Q27", case["dims"], case["periodic"], op, case["nu_p"], case["sigma_y"], m=case["m"],
                          g=case["g"], precision=precision, scheme="AA", layout="COMPACT", **kw)

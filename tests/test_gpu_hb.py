@@ -81,3 +81,36 @@ def test_irhb_channel_against_analytic(n, K, g, sy):
     print(n, sy, float(np.max(np.abs(ux - ref)) / ref.max()), flush=True)
     assert np.max(np.abs(ux - ref)) <= 4e-3 * ref.max()
     assert np.array_equal(uy.reshape(H, 4)[:, 0].astype(bool), plug)
+
+
+def test_irhb_full_size_bench_geometry():
+    """The bench's IRHB form at full size (D3Q27 256^3 sphere pack, FP64, AA,
+    compact, n = 0.5, K = nu_p) from a seeded random state: two steps (both
+    AA phases) against two oracle steps, every fluid node at the parity bar."""
+    import oracle
+    from paper_1610_01388_amd import inputs, lbm
+    from support import perm_lib_from_oracle, random_state
+    n = 256
+    mask, _ = inputs.sphere_pack((n, n, n), 8.0, 0.7, seed=1)
+    case = inputs.porous_case("IR", n=n, Bi=1.0)
+    P0, _ = random_state(2, n ** 3, 37, amp=1e-3)
+    P0 *= (1 - mask)[None, :]
+    rh = oracle.rheology(oracle.IRHB, case["nu_p"], case["sigma_y"], 0.0, 1e-8, 0.25, case["g"], hb_n=0.5)
+    od = oracle.Domain(2, case["dims"], case["periodic"], rh, mask)
+    od.set_state(P0, None)
+    od.step(2)
+    rho_o, u_o, _, uy_o = od.moments()
+    od.close()
+    dom = lbm.Domain("D3Q27", case["dims"], case["periodic"], "IRHB", case["nu_p"], case["sigma_y"], g=case["g"],
+                     hb_n=0.5)
+    dom.set_mask(mask)
+    dom.write_populations(P0[perm_lib_from_oracle(2)])
+    dom.step(2)
+    rho_g, u_g, _, uy_g = dom.moments()
+    dom.close()
+    fluid = mask == 0
+    print(f"IRHB 256^3: u L2-rel {l2rel(u_g, u_o):.2e}", flush=True)
+    assert l2rel(u_g, u_o) <= 1e-10
+    assert np.max(np.abs(rho_g - rho_o)[fluid]) <= 1e-12
+    assert np.sum(uy_g != uy_o) <= 2
+
